@@ -1,0 +1,179 @@
+/*
+ * sfgen -- scale-free graph generation on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the GPU library libsfgen.so.  It implements the edge generators of
+ * Yoo & Henderson, "Parallel Generation of Massive Scale-Free Graphs":
+ *   - the parallel Barabasi-Albert method (PBA, two-phase preferential
+ *     attachment; section "Parallel Barabasi-Albert (PBA) method", Fig. 1),
+ *   - the Kronecker generator (section "Parallel Kronecker (PK) method",
+ *     Fig. 2), both as the deterministic Kronecker power the paper expands
+ *     and as the stochastic Kronecker model it cites in Related Work,
+ * plus the conversion of an edge list to compressed sparse rows with a
+ * degree histogram (the degree distributions of the Results section, Fig. 3).
+ *
+ * Conventions shared by every entry point:
+ *   - All functions have C linkage, never throw, and return an int status:
+ *     SFG_OK (0) or a negative SFG_E* code.  sfg_last_error() returns a
+ *     thread-local message describing the last failure on the calling thread.
+ *   - Every argument is validated on the host before anything is enqueued.
+ *     On error nothing is enqueued and no output is touched.
+ *   - Pointers documented "device" must point to device memory of the current
+ *     HIP device; "host" pointers are read before the call returns and not
+ *     retained.  The caller owns every buffer.  No entry point allocates
+ *     device memory: scratch space is the caller's workspace, sized by the
+ *     matching *_workspace_bytes function.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued asynchronously on it; faults inside kernels surface at the
+ *     next synchronisation of that stream.
+ *   - id_bytes selects the vertex id type of edge and CSR arrays: 4 = int32,
+ *     8 = int64.  Ids are nonnegative.
+ *   - Every random choice is a draw of the counter-based generator
+ *     Philox4x32-10 (Salmon et al., SC'11) keyed by `seed`; the counter is
+ *     (item_lo, item_hi, x, tag | graph_id << 8).  Outputs are a pure
+ *     function of the arguments: independent of stream, workspace size above
+ *     the minimum, launch configuration and batching.
+ *   - A kernel that waits on another workgroup does so with a bounded spin.
+ *     If the bound is ever exhausted the kernel records a device error and
+ *     exits instead of hanging; sfg_device_error() reports it.
+ */
+#ifndef SFGEN_H
+#define SFGEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SFG_OK = 0,
+    SFG_EINVAL = -1,   /* malformed argument                                 */
+    SFG_ERANGE = -2,   /* a size or id does not fit the chosen types         */
+    SFG_ENOSPACE = -3, /* workspace smaller than *_workspace_bytes           */
+    SFG_EDEVICE = -4   /* the HIP runtime reported an error                  */
+};
+
+enum { SFG_KRON_SAMPLE = 0, SFG_KRON_ENUMERATE = 1 };
+
+enum {
+    SFG_CSR_SYMMETRIZE = 1u, /* add (v,u) for every (u,v)                      */
+    SFG_CSR_SIMPLE = 2u      /* drop self-loops and repeated (u,v) entries      */
+};
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *sfg_last_error(void);
+
+/* ABI version of this header (incremented on incompatible change). */
+int sfg_abi_version(void);
+
+/* Device-side error word: 0 if no kernel has exhausted a bounded wait since
+ * the last call, else a nonzero code.  Synchronises `stream` and clears the
+ * word.  Returns SFG_OK and stores the word in *code. */
+int sfg_device_error(void *stream, uint32_t *code);
+
+/* ------------------------------------------------------------------------
+ * kron_generate -- Kronecker graph edges (section "Parallel Kronecker (PK)
+ * method": Kronecker product of adjacency matrices, Fig. 2).
+ *
+ * n0, initiator: host array of n0*n0 float32, row-major, finite and >= 0.
+ * k:             number of Kronecker levels; vertex ids lie in [0, n0^k).
+ * mode SFG_KRON_SAMPLE: the stochastic model.  Edge e draws one cell per
+ *     level, most significant level first, each with probability
+ *     initiator[r][c] / sum(initiator); level l uses 32-bit word (l mod 4) of
+ *     the Philox block (e, l / 4, tag 1).  A cell is chosen by comparing the
+ *     word against binary64 cumulative thresholds floor(S_c / T * 2^32).
+ *     Row digits make the source id, column digits the destination id.
+ *     Self-loops and repeated edges are kept.  Requires n0 <= 16.
+ * mode SFG_KRON_ENUMERATE: the paper's deterministic Kronecker power.  The
+ *     nonzero cells of the initiator are the seed graph's e0 edges in
+ *     row-major order; edge e (in [0, e0^k)) takes the base-e0 digits of e,
+ *     most significant first, as the seed edge expanded at each iteration.
+ *     This is the order in which the paper's meta-edge stack emits edges.
+ *     num_edges must equal e0^k; requires e0 <= 4096.  seed is unused.
+ * num_edges:     edges to write (sample mode: any count).
+ * src, dst:      device arrays of num_edges ids each (id_bytes wide).
+ * Errors: EINVAL (n0 < 2, k == 0, bad initiator, bad mode, num_edges
+ * mismatch in enumerate mode, NULL buffer with num_edges > 0, graph_id >=
+ * 2^24); ERANGE (n0^k - 1 exceeds the id type).
+ * ---------------------------------------------------------------------- */
+int kron_generate(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges, int mode,
+                  uint64_t seed, uint32_t graph_id, int id_bytes, void *src, void *dst, void *stream);
+
+/* ------------------------------------------------------------------------
+ * pba_generate -- parallel Barabasi-Albert edges (section "Parallel
+ * Barabasi-Albert (PBA) method", Fig. 1).
+ *
+ * The paper's processors are num_parts partitions of contiguous vertex
+ * blocks: partition q holds vertices [floor(q n / P), floor((q+1) n / P)).
+ * Every vertex owns m edges, so the graph has n*m edges; edge e belongs to
+ * vertex e / m (src[e] = e / m).
+ *
+ * Phase 1 (per partition q, slot j of its local edge list A): the first s_q
+ *     slots take the partitions of q's faction list in order; a later slot,
+ *     with probability p_inter, takes a uniformly chosen partition outside
+ *     the faction list (an inter-faction edge), else copies the partition of
+ *     a uniformly chosen earlier slot.  Draw: Philox block (j, q, tag 2):
+ *     word 0 against floor(p_inter * 2^32), words 1-2 as a 64-bit uniform.
+ * Count exchange: c[q][l] = occurrences of l in q's list; partition l
+ *     receives D_l = sum_q c[q][l] requests, divided among requesters in
+ *     ascending requester order.
+ * Phase 2 (per partition l): D_l endpoints chosen by preferential attachment
+ *     over l's vertices, growing from a 2-vertex clique: the t-th arrival is
+ *     local vertex floor(t L_l / D_l) and its endpoint is a uniform entry of
+ *     the endpoint pool of all earlier edges (Philox block (t, l, tag 3)).
+ * Substitution: each occurrence of l in A is replaced, in slot order, by the
+ *     next endpoint of the list l sent to this requester.
+ *
+ * faction_off:     host, num_parts+1 offsets into faction_members, or NULL for
+ *                  the default F(q) = [q].
+ * faction_members: host, faction_off[num_parts] partition ids (each <
+ *                  num_parts); the list of q is the concatenation of the
+ *                  members of q's factions, with repetition.
+ * src, dst:        device, n*m ids each.
+ * workspace:       device, at least pba_workspace_bytes(n, m, num_parts) bytes,
+ *                  256-byte aligned.
+ * Errors: EINVAL (m == 0, num_parts == 0 or > 8192, n < 2*num_parts,
+ * p_inter outside [0,1] or NaN, bad faction table, NULL buffers, graph_id >=
+ * 2^24); ERANGE (n*m or n-1 do not fit, a partition holds >= 2^31 slots);
+ * ENOSPACE.
+ * ---------------------------------------------------------------------- */
+size_t pba_workspace_bytes(uint64_t n, uint32_t m, uint32_t num_parts);
+int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p_inter, const uint32_t *faction_off,
+                 const uint32_t *faction_members, uint64_t seed, uint32_t graph_id, int id_bytes, void *src,
+                 void *dst, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * edges_to_csr -- compressed sparse rows of an edge list.
+ *
+ * The entries (src[e], dst[e]) -- plus (dst[e], src[e]) with
+ * SFG_CSR_SYMMETRIZE, so a self-loop appears twice -- are sorted ascending by
+ * (row, column).  With SFG_CSR_SIMPLE, self-loops are dropped and repeated
+ * entries are kept once.  row_ptr[v] = number of kept entries with row < v
+ * (n+1 values); col holds the kept entries' columns in sorted order.
+ *
+ * n:               vertex count; every id must be < n.
+ * row_ptr:         device, n+1 uint64.
+ * col:             device, capacity num_edges (2*num_edges with SYMMETRIZE)
+ *                  ids of id_bytes; with SIMPLE only row_ptr[n] are written.
+ * degree_hist32:   device [32] uint64 or NULL.  Histogram of the degree
+ *                  deg(v) = #{e : src[e] = v} + #{e : dst[e] = v} of the
+ *                  input edge list: bin 0 counts degree 0, bin b (1..31)
+ *                  counts 2^(b-1) <= deg < 2^b, degrees >= 2^30 go to bin 31.
+ * num_duplicates:  device [1] uint64 or NULL: number of sorted positions
+ *                  (before SIMPLE removal) whose entry equals the previous
+ *                  one.
+ * workspace:       device, edges_to_csr_workspace_bytes(...) bytes.
+ * Errors: EINVAL (n == 0, bad flags, NULL buffers); ERANGE (ids or sizes do
+ * not fit); ENOSPACE.  Ids >= n are not detected (the caller's contract).
+ * ---------------------------------------------------------------------- */
+size_t edges_to_csr_workspace_bytes(uint64_t n, uint64_t num_edges, int id_bytes, uint32_t flags);
+int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes, uint32_t flags,
+                 uint64_t *row_ptr, void *col, uint64_t *degree_hist32, uint64_t *num_duplicates,
+                 void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFGEN_H */

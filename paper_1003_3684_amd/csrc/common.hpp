@@ -1,0 +1,95 @@
+// Shared device and host helpers of libsfgen (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/sfgen.h"
+
+namespace sfg {
+
+// ----------------------------------------------------------------- host side
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int check_launch(const char *what);
+hipStream_t as_stream(void *s);
+int device_cu_count();
+
+// Counter-word tags of the Philox streams.
+enum : uint32_t { TAG_KRON = 1, TAG_PBA1 = 2, TAG_PBA2 = 3, TAG_WEDGE = 4 };
+
+// Device address of the error word that kernels set when a bounded wait runs
+// out (one word per device, defined in runtime.hip).
+uint32_t *device_error_word();
+enum : uint32_t { DEVERR_LOOKBACK = 1u, DEVERR_QUEUE = 2u };
+
+constexpr uint32_t kSpinLimit = 1u << 26;
+
+// Round up to a multiple of 256 bytes (workspace carving granularity).
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Carves consecutive 256-byte aligned regions out of a workspace.
+struct Carver {
+    char *base;
+    size_t used = 0;
+    explicit Carver(void *b) : base(static_cast<char *>(b)) {}
+    template <typename T> T *take(size_t count) {
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += align256(count * sizeof(T));
+        return p;
+    }
+};
+
+// ----------------------------------------------------------------- device side
+
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of
+// (c0,c1,c2,c3) -> (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0))
+// with the key advanced by the Weyl increments between rounds.
+struct Block4 {
+    uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                         uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return Block4{c0, c1, c2, c3};
+}
+
+// floor(U * R / 2^64): an index in [0, R) from a 64-bit uniform.
+__device__ __forceinline__ uint64_t uidx64(uint64_t U, uint64_t R) { return __umul64hi(U, R); }
+
+// floor(w * R / 2^32): an index in [0, R) from a 32-bit uniform.
+__device__ __forceinline__ uint32_t uidx32(uint32_t w, uint32_t R) { return __umulhi(w, R); }
+
+__device__ __forceinline__ uint64_t make_u64(uint32_t lo, uint32_t hi) {
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
+
+// Device-coherent relaxed accesses used for inter-workgroup handshakes.
+template <typename T> __device__ __forceinline__ T load_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> __device__ __forceinline__ void store_agent(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T> __device__ __forceinline__ T fetch_add_agent(T *p, T v) {
+    return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void raise_device_error(uint32_t *word, uint32_t code) {
+    __hip_atomic_fetch_or(word, code, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace sfg

@@ -1,0 +1,683 @@
+// Edge list -> compressed sparse rows, and the degree histogram.
+//
+// Entries (src, dst) are packed into one unsigned key (src << wb) | dst, with
+// wb = bits(n - 1), and sorted by a least-significant-digit radix sort with
+// 8-bit digits over the 2 * wb live bits.  Each digit pass is a single
+// "onesweep" kernel: a workgroup takes the next tile by an atomic ticket,
+// ranks its keys stably in LDS, publishes its per-digit counts and finds the
+// counts of all earlier tiles by decoupled look-back, then writes its keys
+// digit run by digit run (coalesced).  One read and one write of every key
+// per pass -- the pass is HBM-bound.  The first pass reads the edge arrays and
+// packs keys on the fly, so no separate packing pass exists.
+//
+// After the sort, one streaming pass writes the columns, marks the first
+// sorted position of every row (its row start) and counts repeated entries;
+// with SIMPLE it also drops self-loops and repeats, compacting by a
+// look-back scan.  Rows with no entry are filled by a reverse min-scan over
+// the row starts.  The degree histogram counts deg(v) = out + in per vertex
+// (the degree distributions of the paper's Results section).
+#include <string.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace sfg {
+namespace {
+
+constexpr int kPassThreads = 512;
+constexpr int kPassItems = 16;
+constexpr int kPassTile = kPassThreads * kPassItems;  // keys per onesweep tile
+constexpr int kPassWaves = kPassThreads / 64;
+constexpr int kRadix = 256;
+
+constexpr int kFinThreads = 256;
+constexpr int kFinItems = 16;
+constexpr int kFinTile = kFinThreads * kFinItems;
+
+constexpr int kScanChunk = 4096;  // vertices per chunk of the row fill scan
+
+constexpr uint64_t kNoRow = ~0ull;
+
+// Look-back status word: [63:58] pass tag, [57:56] flag, [55:0] count.
+constexpr uint64_t kFlagAgg = 1, kFlagIncl = 2;
+__device__ __forceinline__ uint64_t status_word(uint32_t tag, uint64_t flag, uint64_t v) {
+    return ((uint64_t)tag << 58) | (flag << 56) | v;
+}
+
+
+__device__ __forceinline__ uint32_t count_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+// Sum-scan over the first 256 threads of a block (4 waves): returns the
+// exclusive prefix of v and writes the total to *total.  All threads of the
+// block must call it.
+__device__ uint64_t block_exclusive_scan_256(uint64_t v, uint64_t *s_tmp /*[4]*/, uint64_t *total) {
+    const int tid = threadIdx.x;
+    const uint32_t lane = tid & 63;
+    const int w = tid >> 6;
+    uint64_t x = tid < 256 ? v : 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off, 64);
+        if (lane >= (uint32_t)off) x += y;
+    }
+    if (tid < 256 && lane == 63) s_tmp[w] = x;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i < w) base += s_tmp[i];
+        tot += s_tmp[i];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - (tid < 256 ? v : 0);
+}
+
+template <typename IdT, typename KeyT> __device__ __forceinline__ KeyT pack(IdT u, IdT v, int wb) {
+    using U = typename std::conditional<sizeof(IdT) == 4, uint32_t, uint64_t>::type;
+    return ((KeyT)(U)u << wb) | (KeyT)(U)v;
+}
+
+// Key number idx of the (optionally symmetrized) entry sequence.
+template <typename IdT, typename KeyT, bool SYM>
+__device__ __forceinline__ KeyT entry_key(const IdT *src, const IdT *dst, uint64_t E, uint64_t idx, int wb) {
+    if (!SYM || idx < E) return pack<IdT, KeyT>(src[idx], dst[idx], wb);
+    const uint64_t j = idx - E;
+    return pack<IdT, KeyT>(dst[j], src[j], wb);
+}
+
+// --------------------------------------------------------------------------- prepare
+struct PrepArgs {
+    uint64_t E, N;
+    const void *src, *dst;
+    uint64_t *ghist;   // [passes][256]
+    uint32_t *indeg;   // in-degree counters (directed histogram) or null
+    int wb, passes;
+};
+
+template <typename IdT, typename KeyT, bool SYM>
+__global__ __launch_bounds__(256) void csr_prepare(PrepArgs a) {
+    __shared__ uint32_t s_h[8 * kRadix];
+    for (int i = threadIdx.x; i < 8 * kRadix; i += 256) s_h[i] = 0;
+    __syncthreads();
+    const IdT *src = static_cast<const IdT *>(a.src), *dst = static_cast<const IdT *>(a.dst);
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < a.N; i += stride) {
+        const KeyT k = entry_key<IdT, KeyT, SYM>(src, dst, a.E, i, a.wb);
+        for (int p = 0; p < a.passes; ++p) atomicAdd(&s_h[p * kRadix + (uint32_t)((k >> (8 * p)) & 255)], 1u);
+        if (a.indeg && i < a.E) atomicAdd(&a.indeg[(uint64_t)dst[i]], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < a.passes * kRadix; i += 256)
+        if (s_h[i]) atomicAdd((unsigned long long *)&a.ghist[i], (unsigned long long)s_h[i]);
+}
+
+// Exclusive scan of every pass's digit histogram -> bucket bases.
+__global__ __launch_bounds__(256) void csr_digit_bases(const uint64_t *ghist, uint64_t *gbase) {
+    __shared__ uint64_t s_tmp[4];
+    const int p = blockIdx.x;
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan_256(ghist[p * kRadix + threadIdx.x], s_tmp, &tot);
+    gbase[p * kRadix + threadIdx.x] = ex;
+}
+
+template <typename T> __global__ void fill_kernel(T *p, uint64_t n, T v) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// --------------------------------------------------------------------------- onesweep pass
+struct PassArgs {
+    uint64_t E, N;
+    const void *src, *dst;  // first pass only
+    const void *in;         // later passes
+    void *out;
+    uint64_t *status;       // [tiles][256]
+    const uint64_t *gbase;  // [256] of this pass
+    uint32_t *ticket;
+    uint32_t *err;
+    int wb, shift;
+    uint32_t tag;
+};
+
+template <typename IdT, typename KeyT, bool SYM, bool FIRST>
+__global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
+    __shared__ KeyT s_keys[kPassTile];
+    __shared__ uint32_t s_cnt[kPassWaves][kRadix];
+    __shared__ uint32_t s_off[kRadix];
+    __shared__ uint64_t s_gpos[kRadix];
+    __shared__ uint64_t s_tmp[4];
+    __shared__ uint32_t s_tile;
+
+    const int tid = threadIdx.x;
+    const uint32_t lane = tid & 63;
+    const int w = tid >> 6;
+    if (tid == 0) s_tile = fetch_add_agent(a.ticket, 1u);
+    for (int i = tid; i < kPassWaves * kRadix; i += kPassThreads) (&s_cnt[0][0])[i] = 0;
+    __syncthreads();
+    const uint64_t tile = s_tile;
+    const uint64_t tile_base = tile * kPassTile;
+    const uint64_t wbase = tile_base + (uint64_t)w * 64 * kPassItems;
+
+    KeyT k[kPassItems];
+    uint32_t d[kPassItems];
+#pragma unroll
+    for (int i = 0; i < kPassItems; ++i) {
+        const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
+        if (idx < a.N) {
+            if (FIRST)
+                k[i] = entry_key<IdT, KeyT, SYM>(static_cast<const IdT *>(a.src), static_cast<const IdT *>(a.dst), a.E,
+                                                  idx, a.wb);
+            else
+                k[i] = static_cast<const KeyT *>(a.in)[idx];
+            d[i] = (uint32_t)(k[i] >> a.shift) & 255u;
+        } else {
+            k[i] = 0;
+            d[i] = kRadix;  // no digit
+        }
+    }
+
+    // Stable rank inside the wave: lanes with equal digits are found with 8
+    // ballots; the lowest lane of each group advances the wave's counter.
+    uint32_t r[kPassItems];
+#pragma unroll
+    for (int i = 0; i < kPassItems; ++i) {
+        const uint32_t di = d[i];
+        uint64_t peers = __ballot(di < kRadix);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (di >> b) & 1u;
+            const uint64_t bb = __ballot(bit);
+            peers &= bit ? bb : ~bb;
+        }
+        if (di < kRadix) {
+            const uint32_t below = count_below(peers);
+            const uint32_t old = s_cnt[w][di];
+            r[i] = old + below;
+            if (below == 0) s_cnt[w][di] = old + (uint32_t)__popcll(peers);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // Per digit: prefix over the waves and the tile's count.
+    uint32_t cnt = 0;
+    if (tid < kRadix) {
+        uint32_t acc = 0;
+#pragma unroll
+        for (int wv = 0; wv < kPassWaves; ++wv) {
+            const uint32_t c = s_cnt[wv][tid];
+            s_cnt[wv][tid] = acc;
+            acc += c;
+        }
+        cnt = acc;
+    }
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan_256(cnt, s_tmp, &tot);
+
+    // Decoupled look-back: the number of keys with digit d in earlier tiles.
+    if (tid < kRadix) {
+        s_off[tid] = (uint32_t)ex;
+        uint64_t *st = a.status + tile * kRadix + tid;
+        uint64_t prefix = 0;
+        if (tile == 0) {
+            store_agent(st, status_word(a.tag, kFlagIncl, cnt));
+        } else {
+            store_agent(st, status_word(a.tag, kFlagAgg, cnt));
+            uint64_t j = tile - 1;
+            for (;;) {
+                const uint64_t *pj = a.status + j * kRadix + tid;
+                uint64_t v = load_agent(pj);
+                uint32_t spins = 0;
+                while ((uint32_t)(v >> 58) != a.tag) {
+                    if (++spins > kSpinLimit) {
+                        raise_device_error(a.err, DEVERR_LOOKBACK);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    v = load_agent(pj);
+                }
+                prefix += v & ((1ull << 56) - 1);
+                if (((v >> 56) & 3) == kFlagIncl || (uint32_t)(v >> 58) != a.tag || j == 0) break;
+                --j;
+            }
+            store_agent(st, status_word(a.tag, kFlagIncl, prefix + cnt));
+        }
+        s_gpos[tid] = a.gbase[tid] + prefix - ex;
+    }
+    __syncthreads();
+
+    // Scatter into LDS in digit order, then write digit runs out coalesced.
+#pragma unroll
+    for (int i = 0; i < kPassItems; ++i)
+        if (d[i] < kRadix) s_keys[s_off[d[i]] + s_cnt[w][d[i]] + r[i]] = k[i];
+    __syncthreads();
+    const uint64_t rem = a.N - tile_base;
+    const uint32_t nvalid = rem < (uint64_t)kPassTile ? (uint32_t)rem : (uint32_t)kPassTile;
+    KeyT *out = static_cast<KeyT *>(a.out);
+    for (uint32_t p = tid; p < nvalid; p += kPassThreads) {
+        const KeyT key = s_keys[p];
+        const uint32_t dd = (uint32_t)(key >> a.shift) & 255u;
+        out[s_gpos[dd] + p] = key;
+    }
+}
+
+// --------------------------------------------------------------------------- finish
+struct FinArgs {
+    uint64_t N, n;
+    const void *keys;
+    void *col;
+    uint64_t *rp;       // row starts in output (compacted) positions, kNoRow where no row starts
+    uint64_t *rp_raw;   // row starts in sorted positions, or null
+    uint64_t *dups;     // [1] accumulated, or null
+    uint64_t *status;   // [tiles] look-back words (SIMPLE)
+    uint32_t *ticket;
+    uint32_t *err;
+    int wb;
+};
+
+template <typename IdT, typename KeyT, bool SIMPLE>
+__global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
+    __shared__ KeyT s_keys[kFinTile + 1];
+    __shared__ uint64_t s_tmp[4];
+    __shared__ uint64_t s_base;
+    __shared__ uint32_t s_tile;
+    __shared__ uint32_t s_dups[kFinThreads / 64];
+    const int tid = threadIdx.x;
+    if (tid == 0) s_tile = SIMPLE ? fetch_add_agent(a.ticket, 1u) : blockIdx.x;
+    __syncthreads();
+    const uint64_t tile = s_tile;
+    const uint64_t t0 = tile * kFinTile;
+    const KeyT *K = static_cast<const KeyT *>(a.keys);
+    // Striped (coalesced) load into LDS; slot 0 holds the key before the tile.
+    for (int i = tid; i < kFinTile; i += kFinThreads) {
+        const uint64_t idx = t0 + i;
+        s_keys[i + 1] = idx < a.N ? K[idx] : (KeyT)0;
+    }
+    if (tid == 0) s_keys[0] = t0 > 0 ? K[t0 - 1] : (KeyT)0;
+    __syncthreads();
+    const KeyT mask = ((KeyT)1 << a.wb) - 1;
+    // Blocked view: thread t owns positions t*16 .. t*16+15 of the tile.
+    uint32_t keep_bits = 0, nkeep = 0, ndup = 0;
+#pragma unroll
+    for (int j = 0; j < kFinItems; ++j) {
+        const int p = tid * kFinItems + j;
+        const uint64_t idx = t0 + p;
+        if (idx < a.N) {
+            const KeyT key = s_keys[p + 1], prev = s_keys[p];
+            const bool dup = idx > 0 && key == prev;
+            ndup += dup;
+            const bool keep = !SIMPLE || (!dup && (key >> a.wb) != (key & mask));
+            keep_bits |= (uint32_t)keep << j;
+            nkeep += keep;
+        }
+    }
+    uint64_t cbase = t0;  // output position of this tile's first kept entry
+    if (SIMPLE) {
+        // Exclusive scan of kept counts over the threads, then over tiles.
+        uint64_t tot;
+        const uint64_t lane_pre = 0;
+        (void)lane_pre;
+        const uint64_t ex = block_exclusive_scan_256(nkeep, s_tmp, &tot);
+        if (tid == 0) {
+            uint64_t *st = a.status + tile;
+            uint64_t prefix = 0;
+            if (tile == 0) {
+                store_agent(st, status_word(1, kFlagIncl, tot));
+            } else {
+                store_agent(st, status_word(1, kFlagAgg, tot));
+                uint64_t j = tile - 1;
+                for (;;) {
+                    uint64_t v = load_agent(a.status + j);
+                    uint32_t spins = 0;
+                    while ((uint32_t)(v >> 58) != 1u) {
+                        if (++spins > kSpinLimit) {
+                            raise_device_error(a.err, DEVERR_LOOKBACK);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        v = load_agent(a.status + j);
+                    }
+                    prefix += v & ((1ull << 56) - 1);
+                    if (((v >> 56) & 3) == kFlagIncl || (uint32_t)(v >> 58) != 1u || j == 0) break;
+                    --j;
+                }
+                store_agent(st, status_word(1, kFlagIncl, prefix + tot));
+            }
+            s_base = prefix;
+        }
+        __syncthreads();
+        cbase = s_base + ex;
+    }
+    IdT *col = static_cast<IdT *>(a.col);
+    uint64_t c = SIMPLE ? cbase : t0 + (uint64_t)tid * kFinItems;
+#pragma unroll
+    for (int j = 0; j < kFinItems; ++j) {
+        const int p = tid * kFinItems + j;
+        const uint64_t idx = t0 + p;
+        if (idx < a.N) {
+            const KeyT key = s_keys[p + 1], prev = s_keys[p];
+            const uint64_t row = (uint64_t)(key >> a.wb);
+            if (idx == 0 || row != (uint64_t)(prev >> a.wb)) {
+                a.rp[row] = c;
+                if (a.rp_raw) a.rp_raw[row] = idx;
+            }
+            if (SIMPLE) {
+                if ((keep_bits >> j) & 1u) col[c++] = (IdT)(key & mask);
+            } else {
+                ++c;
+            }
+        }
+    }
+    if (!SIMPLE) {
+        // Columns, striped for coalesced stores.
+        for (int i = tid; i < kFinTile; i += kFinThreads) {
+            const uint64_t idx = t0 + i;
+            if (idx < a.N) col[idx] = (IdT)(s_keys[i + 1] & mask);
+        }
+    }
+    if (a.dups) {
+        uint32_t x = ndup;
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if ((tid & 63) == 0) s_dups[tid >> 6] = x;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t t = 0;
+            for (int i = 0; i < kFinThreads / 64; ++i) t += s_dups[i];
+            if (t) atomicAdd((unsigned long long *)a.dups, (unsigned long long)t);
+        }
+    }
+    // The last tile closes row n.
+    if (t0 + kFinTile >= a.N && tid == kFinThreads - 1) {
+        if (SIMPLE) {
+            // total kept = base of this tile + kept in this tile
+            uint64_t tail = cbase;
+            for (int j = 0; j < kFinItems; ++j) tail += (keep_bits >> j) & 1u;
+            a.rp[a.n] = tail;
+        } else {
+            a.rp[a.n] = a.N;
+        }
+        if (a.rp_raw) a.rp_raw[a.n] = a.N;
+    }
+}
+
+// --------------------------------------------------------------------------- row fill
+// rp[v] = kNoRow for rows without an entry; afterwards rp[v] = the start of
+// the next row that has one (a reverse running minimum; rp[n] is always set).
+__global__ __launch_bounds__(256) void rowfill_reduce(const uint64_t *rp, uint64_t n1, uint64_t *cmin) {
+    __shared__ uint64_t s[256];
+    const uint64_t c0 = (uint64_t)blockIdx.x * kScanChunk;
+    uint64_t m = kNoRow;
+    for (uint64_t v = c0 + threadIdx.x; v < c0 + kScanChunk && v < n1; v += 256) m = min(m, rp[v]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) s[threadIdx.x] = min(s[threadIdx.x], s[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cmin[blockIdx.x] = s[0];
+}
+
+// Exclusive reverse min-scan of the chunk minima (single block).
+__global__ __launch_bounds__(1024) void rowfill_chunks(uint64_t *cmin, uint64_t nchunks) {
+    __shared__ uint64_t s[1024];
+    const uint64_t per = (nchunks + 1023) / 1024;
+    const uint64_t lo = (uint64_t)threadIdx.x * per, hi = min(lo + per, nchunks);
+    uint64_t m = kNoRow;
+    for (uint64_t c = lo; c < hi; ++c) m = min(m, cmin[c]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    // inclusive suffix min over threads
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint64_t other = threadIdx.x + off < 1024 ? s[threadIdx.x + off] : kNoRow;
+        __syncthreads();
+        s[threadIdx.x] = min(s[threadIdx.x], other);
+        __syncthreads();
+    }
+    uint64_t run = threadIdx.x + 1 < 1024 ? s[threadIdx.x + 1] : kNoRow;
+    for (uint64_t c = hi; c > lo; --c) {
+        const uint64_t x = cmin[c - 1];
+        cmin[c - 1] = run;  // minimum over later chunks
+        run = min(run, x);
+    }
+}
+
+__global__ __launch_bounds__(256) void rowfill_apply(uint64_t *rp, uint64_t n1, const uint64_t *cnext) {
+    __shared__ uint64_t s[256];
+    constexpr int per = kScanChunk / 256;
+    const uint64_t c0 = (uint64_t)blockIdx.x * kScanChunk;
+    const uint64_t v0 = c0 + (uint64_t)threadIdx.x * per;
+    uint64_t x[per];
+    uint64_t m = kNoRow;
+#pragma unroll
+    for (int j = per - 1; j >= 0; --j) {
+        const uint64_t v = v0 + j;
+        x[j] = v < n1 ? rp[v] : kNoRow;
+        m = min(m, x[j]);
+    }
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint64_t other = threadIdx.x + off < 256 ? s[threadIdx.x + off] : kNoRow;
+        __syncthreads();
+        s[threadIdx.x] = min(s[threadIdx.x], other);
+        __syncthreads();
+    }
+    uint64_t run = min(cnext[blockIdx.x], threadIdx.x + 1 < 256 ? s[threadIdx.x + 1] : kNoRow);
+#pragma unroll
+    for (int j = per - 1; j >= 0; --j) {
+        const uint64_t v = v0 + j;
+        run = min(run, x[j]);
+        if (v < n1) rp[v] = run;
+    }
+}
+
+// --------------------------------------------------------------------------- degree histogram
+__device__ __forceinline__ int log2_bin(uint64_t d) {
+    if (d == 0) return 0;
+    const int b = 64 - __clzll(d);  // floor(log2 d) + 1
+    return b > 31 ? 31 : b;
+}
+
+__global__ __launch_bounds__(256) void degree_hist_kernel(const uint64_t *rp_raw, const uint32_t *indeg, uint64_t n,
+                                                          uint64_t *hist) {
+    __shared__ uint32_t s_h[32];
+    if (threadIdx.x < 32) s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * 256;
+    for (uint64_t v = (uint64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += stride) {
+        uint64_t deg = rp_raw[v + 1] - rp_raw[v];
+        if (indeg) deg += indeg[v];
+        atomicAdd(&s_h[log2_bin(deg)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x < 32 && s_h[threadIdx.x]) atomicAdd((unsigned long long *)&hist[threadIdx.x], (unsigned long long)s_h[threadIdx.x]);
+}
+
+// --------------------------------------------------------------------------- host
+int bits_for(uint64_t n) {  // bits to hold ids in [0, n)
+    int b = 1;
+    while (b < 64 && (n - 1) >> b) ++b;
+    return b;
+}
+
+struct Plan {
+    uint64_t n, E, N;
+    int wb, kb, passes, key_bytes;
+    bool sym, simple, hist, directed_hist;
+    uint64_t pass_tiles, fin_tiles, chunks;
+    // workspace carving
+    size_t off_keysA, off_keysB, off_status, off_ghist, off_gbase, off_tickets, off_indeg, off_rpraw, off_rpc,
+        off_cmin, off_fstatus, total;
+};
+
+Plan make_plan(uint64_t n, uint64_t E, int id_bytes, uint32_t flags, bool want_hist) {
+    Plan p;
+    memset(&p, 0, sizeof(p));
+    p.n = n;
+    p.E = E;
+    p.sym = flags & SFG_CSR_SYMMETRIZE;
+    p.simple = flags & SFG_CSR_SIMPLE;
+    p.N = p.sym ? 2 * E : E;
+    p.wb = bits_for(n);
+    p.kb = 2 * p.wb;
+    p.passes = (p.kb + 7) / 8;
+    p.key_bytes = p.kb <= 32 ? 4 : 8;
+    p.hist = want_hist;
+    p.directed_hist = want_hist && !p.sym;
+    p.pass_tiles = (p.N + kPassTile - 1) / kPassTile;
+    p.fin_tiles = (p.N + kFinTile - 1) / kFinTile;
+    p.chunks = (n + 1 + kScanChunk - 1) / kScanChunk;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t r = o;
+        o += align256(bytes);
+        return r;
+    };
+    p.off_keysA = take(p.N * p.key_bytes);
+    p.off_keysB = take(p.N * p.key_bytes);
+    p.off_status = take(std::max<uint64_t>(p.pass_tiles, 1) * kRadix * 8);
+    p.off_ghist = take(8 * kRadix * 8);
+    p.off_gbase = take(8 * kRadix * 8);
+    p.off_tickets = take(16 * 4);
+    p.off_indeg = take(p.directed_hist ? n * 4 : 0);
+    p.off_rpraw = take(want_hist && p.simple ? (n + 1) * 8 : 0);
+    p.off_rpc = take(0);
+    p.off_cmin = take(std::max<uint64_t>(p.chunks, 1) * 8);
+    p.off_fstatus = take(p.simple ? std::max<uint64_t>(p.fin_tiles, 1) * 8 : 0);
+    p.total = o;
+    (void)id_bytes;
+    return p;
+}
+
+int fill_grid(uint64_t n) {
+    const uint64_t want = (n + 255) / 256;
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>(want, (uint64_t)device_cu_count() * 8));
+}
+
+template <typename T> void fill(T *p, uint64_t n, T v, hipStream_t s) {
+    if (n) fill_kernel<T><<<fill_grid(n), 256, 0, s>>>(p, n, v);
+}
+
+void row_fill(uint64_t *rp, uint64_t n1, uint64_t *cmin, uint64_t chunks, hipStream_t s) {
+    rowfill_reduce<<<(int)chunks, 256, 0, s>>>(rp, n1, cmin);
+    rowfill_chunks<<<1, 1024, 0, s>>>(cmin, chunks);
+    rowfill_apply<<<(int)chunks, 256, 0, s>>>(rp, n1, cmin);
+}
+
+template <typename IdT, typename KeyT>
+int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, void *col, uint64_t *hist,
+            uint64_t *dups, char *ws, hipStream_t s) {
+    uint32_t *err = device_error_word();
+    KeyT *keysA = reinterpret_cast<KeyT *>(ws + P.off_keysA);
+    KeyT *keysB = reinterpret_cast<KeyT *>(ws + P.off_keysB);
+    uint64_t *status = reinterpret_cast<uint64_t *>(ws + P.off_status);
+    uint64_t *ghist = reinterpret_cast<uint64_t *>(ws + P.off_ghist);
+    uint64_t *gbase = reinterpret_cast<uint64_t *>(ws + P.off_gbase);
+    uint32_t *tickets = reinterpret_cast<uint32_t *>(ws + P.off_tickets);
+    uint32_t *indeg = P.directed_hist ? reinterpret_cast<uint32_t *>(ws + P.off_indeg) : nullptr;
+    uint64_t *rp_raw_ws = (P.hist && P.simple) ? reinterpret_cast<uint64_t *>(ws + P.off_rpraw) : nullptr;
+    uint64_t *cmin = reinterpret_cast<uint64_t *>(ws + P.off_cmin);
+    uint64_t *fstatus = P.simple ? reinterpret_cast<uint64_t *>(ws + P.off_fstatus) : nullptr;
+
+    // Clear counters, histograms and look-back words (fill kernels, so the
+    // sequence stays valid under stream capture).
+    fill<uint64_t>(ghist, 8 * kRadix, 0, s);
+    fill<uint32_t>(tickets, 16, 0, s);
+    if (P.N) fill<uint64_t>(status, P.pass_tiles * kRadix, 0, s);
+    if (fstatus && P.N) fill<uint64_t>(fstatus, P.fin_tiles, 0, s);
+    if (indeg) fill<uint32_t>(indeg, P.n, 0, s);
+    if (dups) fill<uint64_t>(dups, 1, 0, s);
+    if (hist) fill<uint64_t>(hist, 32, 0, s);
+    fill<uint64_t>(row_ptr, P.n + 1, kNoRow, s);
+    if (rp_raw_ws) fill<uint64_t>(rp_raw_ws, P.n + 1, kNoRow, s);
+
+    if (P.N > 0) {
+        PrepArgs pa{P.E, P.N, src, dst, ghist, indeg, P.wb, P.passes};
+        const int pg = fill_grid(P.N);
+        if (P.sym)
+            csr_prepare<IdT, KeyT, true><<<pg, 256, 0, s>>>(pa);
+        else
+            csr_prepare<IdT, KeyT, false><<<pg, 256, 0, s>>>(pa);
+        csr_digit_bases<<<P.passes, 256, 0, s>>>(ghist, gbase);
+
+        // Ping-pong so that the last pass lands in keysA.
+        for (int p = 0; p < P.passes; ++p) {
+            const int remaining = P.passes - 1 - p;  // passes after this one
+            KeyT *out = (remaining % 2 == 0) ? keysA : keysB;
+            KeyT *in = (remaining % 2 == 0) ? keysB : keysA;
+            PassArgs a{P.E, P.N, src, dst, in, out, status, gbase + p * kRadix, tickets + p, err, P.wb, 8 * p,
+                       (uint32_t)(p + 1)};
+            const int g = (int)P.pass_tiles;
+            if (p == 0) {
+                if (P.sym)
+                    radix_pass<IdT, KeyT, true, true><<<g, kPassThreads, 0, s>>>(a);
+                else
+                    radix_pass<IdT, KeyT, false, true><<<g, kPassThreads, 0, s>>>(a);
+            } else {
+                radix_pass<IdT, KeyT, false, false><<<g, kPassThreads, 0, s>>>(a);
+            }
+        }
+        FinArgs fa{P.N, P.n, keysA, col, row_ptr, P.simple ? rp_raw_ws : nullptr, dups, fstatus, tickets + 15, err,
+                   P.wb};
+        if (P.simple)
+            csr_finish<IdT, KeyT, true><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa);
+        else
+            csr_finish<IdT, KeyT, false><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa);
+    } else {
+        fill<uint64_t>(row_ptr + P.n, 1, 0, s);
+        if (rp_raw_ws) fill<uint64_t>(rp_raw_ws + P.n, 1, 0, s);
+    }
+    row_fill(row_ptr, P.n + 1, cmin, P.chunks, s);
+    if (hist) {
+        const uint64_t *raw = row_ptr;
+        if (rp_raw_ws) {
+            row_fill(rp_raw_ws, P.n + 1, cmin, P.chunks, s);
+            raw = rp_raw_ws;
+        }
+        degree_hist_kernel<<<fill_grid(P.n), 256, 0, s>>>(raw, indeg, P.n, hist);
+    }
+    return check_launch("edges_to_csr");
+}
+
+}  // namespace
+}  // namespace sfg
+
+using namespace sfg;
+
+extern "C" size_t edges_to_csr_workspace_bytes(uint64_t n, uint64_t num_edges, int id_bytes, uint32_t flags) {
+    if (n == 0) return 0;
+    return make_plan(n, num_edges, id_bytes, flags, true).total;
+}
+
+extern "C" int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes,
+                            uint32_t flags, uint64_t *row_ptr, void *col, uint64_t *degree_hist32,
+                            uint64_t *num_duplicates, void *workspace, size_t workspace_bytes, void *stream) {
+    if (n == 0) return fail(SFG_EINVAL, "edges_to_csr: n must be >= 1");
+    if (id_bytes != 4 && id_bytes != 8) return fail(SFG_EINVAL, "edges_to_csr: id_bytes must be 4 or 8");
+    if (flags & ~(uint32_t)(SFG_CSR_SYMMETRIZE | SFG_CSR_SIMPLE)) return fail(SFG_EINVAL, "edges_to_csr: bad flags");
+    if (!row_ptr) return fail(SFG_EINVAL, "edges_to_csr: row_ptr is NULL");
+    if (num_edges > 0 && (!src || !dst || !col)) return fail(SFG_EINVAL, "edges_to_csr: NULL edge or col buffer");
+    if (id_bytes == 4 && n - 1 > 0x7FFFFFFFull) return fail(SFG_ERANGE, "edges_to_csr: n does not fit int32 ids");
+    if (n > (1ull << 32)) return fail(SFG_ERANGE, "edges_to_csr: n > 2^32 does not fit a 64-bit key");
+    if (num_edges > (1ull << 54)) return fail(SFG_ERANGE, "edges_to_csr: too many edges");
+    const bool sym = flags & SFG_CSR_SYMMETRIZE;
+    const uint64_t N = sym ? 2 * num_edges : num_edges;
+    if ((N + kPassTile - 1) / kPassTile > 0x7FFFFFFFull) return fail(SFG_ERANGE, "edges_to_csr: too many tiles");
+    Plan P = make_plan(n, num_edges, id_bytes, flags, degree_hist32 != nullptr);
+    if (P.total > 0 && !workspace) return fail(SFG_EINVAL, "edges_to_csr: workspace is NULL");
+    if (workspace_bytes < P.total)
+        return fail(SFG_ENOSPACE, "edges_to_csr: workspace has %zu bytes, needs %zu", workspace_bytes, P.total);
+    if (!device_error_word()) return fail(SFG_EDEVICE, "edges_to_csr: no device");
+    hipStream_t s = as_stream(stream);
+    char *ws = static_cast<char *>(workspace);
+    if (P.key_bytes == 4) {
+        if (id_bytes == 4) return run_csr<int32_t, uint32_t>(P, src, dst, row_ptr, col, degree_hist32, num_duplicates, ws, s);
+        return run_csr<int64_t, uint32_t>(P, src, dst, row_ptr, col, degree_hist32, num_duplicates, ws, s);
+    }
+    if (id_bytes == 4) return run_csr<int32_t, uint64_t>(P, src, dst, row_ptr, col, degree_hist32, num_duplicates, ws, s);
+    return run_csr<int64_t, uint64_t>(P, src, dst, row_ptr, col, degree_hist32, num_duplicates, ws, s);
+}

@@ -1,0 +1,367 @@
+// Kronecker edge generation (section "Parallel Kronecker (PK) method", Fig. 2).
+//
+// Every edge is computed independently from its index e, so one launch covers
+// any range of edges and needs no communication -- the one-GPU limit of the
+// paper's processor groups, which split the meta-edges of each iteration
+// among processors.
+//
+// Sample mode: per level one 32-bit Philox word chooses a cell of the
+// initiator by comparison against cumulative thresholds; the row digit goes to
+// the source id and the column digit to the destination id, most significant
+// level first.  The kernel is bound by integer ALU work (Philox and the
+// threshold compares), not by its 2 * id_bytes of HBM writes per edge.
+//
+// Enumerate mode: the base-e0 digits of e select seed edges, which is exactly
+// the order in which the paper's depth-first meta-edge stack emits them.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+
+namespace sfg {
+namespace {
+
+constexpr int kBlock = 256;
+
+// Thresholds of the sample mode in the form the kernels use.  With the
+// distinct cumulative thresholds v_1 < v_2 < ... (those below 2^32, v_i >= 1),
+// a word w selects bucket b = #{i : w > v_i - 1}; the cell is lut[b].
+struct SampleTable {
+    uint32_t nt = 0;             // number of distinct thresholds >= 1
+    uint32_t tm1[255];           // v_i - 1, ascending
+    uint8_t row[256], col[256];  // cell digits of bucket b
+};
+
+int build_sample_table(uint32_t n0, const float *W, SampleTable &tab) {
+    const uint32_t C = n0 * n0;
+    std::vector<double> run(C);
+    double S = 0.0;
+    for (uint32_t c = 0; c < C; ++c) {
+        const double w = (double)W[c];
+        if (!(w >= 0.0) || std::isinf(w)) return fail(SFG_EINVAL, "kron_generate: initiator[%u] is not finite and >= 0", c);
+        S = S + w;  // left-to-right binary64 running sum
+        run[c] = S;
+    }
+    if (!(S > 0.0) || std::isinf(S)) return fail(SFG_EINVAL, "kron_generate: initiator sums to zero or overflows");
+    // thr[c] = floor(S_c / T * 2^32) for c < C-1; thr[C-1] = 2^32 (never reached).
+    std::vector<uint64_t> thr(C);
+    for (uint32_t c = 0; c + 1 < C; ++c) {
+        const double q = run[c] / S;
+        const double t = std::floor(q * 4294967296.0);
+        thr[c] = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
+    }
+    thr[C - 1] = 1ull << 32;
+    // cell(w) = #{c < C-1 : w >= thr[c]}; thresholds equal to 0 always count.
+    uint32_t base = 0;
+    std::vector<uint64_t> distinct;
+    for (uint32_t c = 0; c + 1 < C; ++c) {
+        if (thr[c] == 0) {
+            ++base;
+        } else if (thr[c] < (1ull << 32)) {
+            if (distinct.empty() || distinct.back() != thr[c]) distinct.push_back(thr[c]);
+        }
+    }
+    tab.nt = (uint32_t)distinct.size();
+    for (uint32_t i = 0; i < tab.nt; ++i) tab.tm1[i] = (uint32_t)(distinct[i] - 1);
+    for (uint32_t b = 0; b <= tab.nt; ++b) {
+        // w in [v_b, v_{b+1}) (with v_0 = 0): the cell counts thresholds <= v_b.
+        const uint64_t vb = b == 0 ? 0 : distinct[b - 1];
+        uint32_t cell = 0;
+        for (uint32_t c = 0; c + 1 < C; ++c)
+            if (thr[c] <= vb) ++cell;
+        if (b == 0) cell = base;
+        tab.row[b] = (uint8_t)(cell / n0);
+        tab.col[b] = (uint8_t)(cell % n0);
+    }
+    return SFG_OK;
+}
+
+// Kernel arguments of the register path (at most 15 distinct thresholds and
+// digits below 16): thresholds live in scalar registers, the bucket-to-digit
+// map in two 64-bit nibble tables.
+struct FastArgs {
+    uint64_t num_edges;
+    uint32_t key0, key1, tagword, k;
+    uint32_t n0, shift;
+    uint32_t tm1[15];
+    uint64_t lut_row, lut_col;
+};
+
+template <int NT> __device__ __forceinline__ uint32_t bucket_of(uint32_t w, const uint32_t (&t)[15]) {
+    uint32_t b = 0;
+#pragma unroll
+    for (int i = 0; i < NT; ++i) b += (w > t[i]) ? 1u : 0u;
+    return b;
+}
+
+template <typename IdT, typename AccT, bool POW2, int NT>
+__global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__restrict__ src, IdT *__restrict__ dst) {
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < a.num_edges; e += stride) {
+        AccT u = 0, v = 0;
+        const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
+        for (uint32_t blk = 0; blk * 4 < a.k; ++blk) {
+            const Block4 r = philox(elo, ehi, blk, a.tagword, a.key0, a.key1);
+            const uint32_t ws[4] = {r.w0, r.w1, r.w2, r.w3};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (blk * 4 + i < a.k) {
+                    const uint32_t b = bucket_of<NT>(ws[i], a.tm1);
+                    const AccT rd = (AccT)((a.lut_row >> (4 * b)) & 15u);
+                    const AccT cd = (AccT)((a.lut_col >> (4 * b)) & 15u);
+                    if (POW2) {
+                        u = (u << a.shift) | rd;
+                        v = (v << a.shift) | cd;
+                    } else {
+                        u = u * a.n0 + rd;
+                        v = v * a.n0 + cd;
+                    }
+                }
+            }
+        }
+        src[e] = (IdT)u;
+        dst[e] = (IdT)v;
+    }
+}
+
+// General path: up to 255 distinct thresholds, searched in LDS.
+struct GeneralArgs {
+    uint64_t num_edges;
+    uint32_t key0, key1, tagword, k;
+    uint32_t n0, nt;
+};
+
+template <typename IdT, typename AccT>
+__global__ __launch_bounds__(kBlock) void kron_sample_general(GeneralArgs a, SampleTable tab, IdT *__restrict__ src,
+                                                              IdT *__restrict__ dst) {
+    __shared__ uint32_t s_t[256];
+    __shared__ uint8_t s_row[256], s_col[256];
+    for (uint32_t i = threadIdx.x; i < 256; i += kBlock) {
+        s_t[i] = i < a.nt ? tab.tm1[i] : 0xFFFFFFFFu;
+        s_row[i] = tab.row[i];
+        s_col[i] = tab.col[i];
+    }
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < a.num_edges; e += stride) {
+        AccT u = 0, v = 0;
+        const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
+        for (uint32_t blk = 0; blk * 4 < a.k; ++blk) {
+            const Block4 r = philox(elo, ehi, blk, a.tagword, a.key0, a.key1);
+            const uint32_t ws[4] = {r.w0, r.w1, r.w2, r.w3};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if (blk * 4 + i < a.k) {
+                    // b = #{j : w > s_t[j]}: binary search over the padded sorted table.
+                    const uint32_t w = ws[i];
+                    uint32_t b = 0;
+#pragma unroll
+                    for (uint32_t step = 128; step > 0; step >>= 1)
+                        if (w > s_t[b + step - 1]) b += step;
+                    u = u * a.n0 + s_row[b];
+                    v = v * a.n0 + s_col[b];
+                }
+            }
+        }
+        src[e] = (IdT)u;
+        dst[e] = (IdT)v;
+    }
+}
+
+// Enumerate mode.  mask holds the 0/1 seed matrix (n0 <= 64) as bits; every
+// block rebuilds the row-major list of nonzero cells in LDS.
+struct EnumArgs {
+    uint64_t num_edges;
+    uint32_t n0, e0, k;
+    uint32_t mask[128];
+};
+
+template <typename IdT, typename IdxT>
+__global__ __launch_bounds__(kBlock) void kron_enumerate_kernel(EnumArgs a, IdT *__restrict__ src,
+                                                                IdT *__restrict__ dst) {
+    __shared__ uint16_t s_r[4096], s_c[4096];
+    __shared__ uint32_t s_wordbase[129];
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int i = 0; i < 128; ++i) {
+            s_wordbase[i] = acc;
+            acc += __popc(a.mask[i]);
+        }
+        s_wordbase[128] = acc;
+    }
+    __syncthreads();
+    for (uint32_t wi = threadIdx.x; wi < 128; wi += kBlock) {
+        uint32_t m = a.mask[wi], idx = s_wordbase[wi];
+        while (m) {
+            const uint32_t bit = __ffs(m) - 1;
+            m &= m - 1;
+            const uint32_t cell = wi * 32 + bit;
+            s_r[idx] = (uint16_t)(cell / a.n0);
+            s_c[idx] = (uint16_t)(cell % a.n0);
+            ++idx;
+        }
+    }
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < a.num_edges; e += stride) {
+        IdxT rest = (IdxT)e;
+        uint64_t u = 0, v = 0, pw = 1;
+        for (uint32_t l = 0; l < a.k; ++l) {  // least significant digit first
+            const IdxT q = rest / a.e0;
+            const uint32_t d = (uint32_t)(rest - q * a.e0);
+            rest = q;
+            u += (uint64_t)s_r[d] * pw;
+            v += (uint64_t)s_c[d] * pw;
+            pw *= a.n0;
+        }
+        src[e] = (IdT)u;
+        dst[e] = (IdT)v;
+    }
+}
+
+// n0^k, or 0 if it exceeds 2^64 - 1.
+uint64_t upow(uint64_t b, uint32_t k) {
+    uint64_t r = 1;
+    for (uint32_t i = 0; i < k; ++i) {
+        if (r > UINT64_MAX / b) return 0;
+        r *= b;
+    }
+    return r;
+}
+
+int grid_for(uint64_t items) {
+    const uint64_t want = (items + kBlock - 1) / kBlock;
+    const uint64_t cap = (uint64_t)device_cu_count() * 16;
+    return (int)std::max<uint64_t>(1, std::min(want, cap));
+}
+
+template <typename IdT, typename AccT, bool POW2>
+void launch_fast(const FastArgs &a, uint32_t nt, void *src, void *dst, hipStream_t s) {
+    const int g = grid_for(a.num_edges);
+    IdT *S = static_cast<IdT *>(src), *D = static_cast<IdT *>(dst);
+    if (nt <= 3)
+        kron_sample_fast<IdT, AccT, POW2, 3><<<g, kBlock, 0, s>>>(a, S, D);
+    else if (nt <= 8)
+        kron_sample_fast<IdT, AccT, POW2, 8><<<g, kBlock, 0, s>>>(a, S, D);
+    else
+        kron_sample_fast<IdT, AccT, POW2, 15><<<g, kBlock, 0, s>>>(a, S, D);
+}
+
+template <typename IdT, typename AccT>
+void launch_fast_any(const FastArgs &a, bool pow2, uint32_t nt, void *src, void *dst, hipStream_t s) {
+    if (pow2)
+        launch_fast<IdT, AccT, true>(a, nt, src, dst, s);
+    else
+        launch_fast<IdT, AccT, false>(a, nt, src, dst, s);
+}
+
+}  // namespace
+}  // namespace sfg
+
+using namespace sfg;
+
+extern "C" int kron_generate(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges, int mode,
+                             uint64_t seed, uint32_t graph_id, int id_bytes, void *src, void *dst, void *stream) {
+    if (n0 < 2) return fail(SFG_EINVAL, "kron_generate: n0 must be >= 2 (got %u)", n0);
+    if (k == 0) return fail(SFG_EINVAL, "kron_generate: k must be >= 1");
+    if (!initiator) return fail(SFG_EINVAL, "kron_generate: initiator is NULL");
+    if (mode != SFG_KRON_SAMPLE && mode != SFG_KRON_ENUMERATE) return fail(SFG_EINVAL, "kron_generate: bad mode %d", mode);
+    if (id_bytes != 4 && id_bytes != 8) return fail(SFG_EINVAL, "kron_generate: id_bytes must be 4 or 8");
+    if (graph_id >= (1u << 24)) return fail(SFG_EINVAL, "kron_generate: graph_id must be < 2^24");
+    if (num_edges > 0 && (!src || !dst)) return fail(SFG_EINVAL, "kron_generate: NULL output buffer");
+    const uint64_t nv = upow(n0, k);
+    const uint64_t max_id = id_bytes == 4 ? 0x7FFFFFFFull : 0x7FFFFFFFFFFFFFFFull;
+    if (nv == 0 || nv - 1 > max_id)
+        return fail(SFG_ERANGE, "kron_generate: %u^%u vertices do not fit %d-byte ids", n0, k, id_bytes);
+    const bool acc32 = nv <= (1ull << 32);
+    const bool pow2 = (n0 & (n0 - 1)) == 0;
+    uint32_t shift = 0;
+    while ((1u << shift) < n0) ++shift;
+    hipStream_t s = as_stream(stream);
+
+    if (mode == SFG_KRON_ENUMERATE) {
+        if (n0 > 64) return fail(SFG_EINVAL, "kron_generate: enumerate mode needs n0 <= 64");
+        EnumArgs a;
+        memset(&a, 0, sizeof(a));
+        uint32_t e0 = 0;
+        for (uint32_t c = 0; c < n0 * n0; ++c) {
+            const float w = initiator[c];
+            if (!(w >= 0.0f) || std::isinf(w)) return fail(SFG_EINVAL, "kron_generate: initiator[%u] is not finite and >= 0", c);
+            if (w > 0.0f) {
+                a.mask[c / 32] |= 1u << (c % 32);
+                ++e0;
+            }
+        }
+        if (e0 == 0) return fail(SFG_EINVAL, "kron_generate: the seed graph has no edge");
+        const uint64_t ne = upow(e0, k);
+        if (ne == 0 || ne != num_edges)
+            return fail(SFG_EINVAL, "kron_generate: enumerate mode writes e0^k = %u^%u edges, num_edges is %llu", e0, k,
+                        (unsigned long long)num_edges);
+        a.num_edges = num_edges;
+        a.n0 = n0;
+        a.e0 = e0;
+        a.k = k;
+        const int g = grid_for(num_edges);
+        const bool idx32 = ne <= (1ull << 32);
+        if (id_bytes == 4 && idx32)
+            kron_enumerate_kernel<int32_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst);
+        else if (id_bytes == 4)
+            kron_enumerate_kernel<int32_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst);
+        else if (idx32)
+            kron_enumerate_kernel<int64_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
+        else
+            kron_enumerate_kernel<int64_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
+        return check_launch("kron_generate(enumerate)");
+    }
+
+    if (n0 > 16) return fail(SFG_EINVAL, "kron_generate: sample mode needs n0 <= 16");
+    SampleTable tab;
+    memset(&tab, 0, sizeof(tab));
+    int rc = build_sample_table(n0, initiator, tab);
+    if (rc != SFG_OK) return rc;
+    if (num_edges == 0) return SFG_OK;
+    const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+    const uint32_t tagword = TAG_KRON | (graph_id << 8);
+    if (tab.nt <= 15) {
+        FastArgs a;
+        memset(&a, 0, sizeof(a));
+        a.num_edges = num_edges;
+        a.key0 = key0;
+        a.key1 = key1;
+        a.tagword = tagword;
+        a.k = k;
+        a.n0 = n0;
+        a.shift = shift;
+        for (int i = 0; i < 15; ++i) a.tm1[i] = (uint32_t)i < tab.nt ? tab.tm1[i] : 0xFFFFFFFFu;
+        for (uint32_t b = 0; b <= tab.nt; ++b) {
+            a.lut_row |= (uint64_t)tab.row[b] << (4 * b);
+            a.lut_col |= (uint64_t)tab.col[b] << (4 * b);
+        }
+        if (id_bytes == 4)
+            launch_fast_any<int32_t, uint32_t>(a, pow2, tab.nt, src, dst, s);
+        else if (acc32)
+            launch_fast_any<int64_t, uint32_t>(a, pow2, tab.nt, src, dst, s);
+        else
+            launch_fast_any<int64_t, uint64_t>(a, pow2, tab.nt, src, dst, s);
+        return check_launch("kron_generate(sample)");
+    }
+    GeneralArgs a;
+    a.num_edges = num_edges;
+    a.key0 = key0;
+    a.key1 = key1;
+    a.tagword = tagword;
+    a.k = k;
+    a.n0 = n0;
+    a.nt = tab.nt;
+    const int g = grid_for(num_edges);
+    if (id_bytes == 4)
+        kron_sample_general<int32_t, uint32_t><<<g, kBlock, 0, s>>>(a, tab, (int32_t *)src, (int32_t *)dst);
+    else if (acc32)
+        kron_sample_general<int64_t, uint32_t><<<g, kBlock, 0, s>>>(a, tab, (int64_t *)src, (int64_t *)dst);
+    else
+        kron_sample_general<int64_t, uint64_t><<<g, kBlock, 0, s>>>(a, tab, (int64_t *)src, (int64_t *)dst);
+    return check_launch("kron_generate(sample, general)");
+}

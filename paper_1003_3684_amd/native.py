@@ -1,0 +1,178 @@
+"""Thin Python binding of libsfgen.so.
+
+Argument marshalling only: torch supplies device memory and the current HIP
+stream; every step of generation and CSR construction runs in the library's
+HIP kernels.  Function names follow the C ABI in include/sfgen.h.  There is no
+CPU fallback: if the library or a GPU is missing, calls raise.
+"""
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsfgen.so")
+
+SFG_OK, SFG_EINVAL, SFG_ERANGE, SFG_ENOSPACE, SFG_EDEVICE = 0, -1, -2, -3, -4
+KRON_SAMPLE, KRON_ENUMERATE = 0, 1
+CSR_SYMMETRIZE, CSR_SIMPLE = 1, 2
+
+_ERRNAMES = {SFG_EINVAL: "EINVAL", SFG_ERANGE: "ERANGE", SFG_ENOSPACE: "ENOSPACE", SFG_EDEVICE: "EDEVICE"}
+
+
+class SfgenError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+_vp, _u32, _u64, _i32, _dbl, _sz = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int, C.c_double, C.c_size_t
+
+# name -> (restype, argtypes); the order follows include/sfgen.h.
+SIGNATURES = {
+    "sfg_last_error": (C.c_char_p, []),
+    "sfg_abi_version": (_i32, []),
+    "sfg_device_error": (_i32, [_vp, C.POINTER(_u32)]),
+    "kron_generate": (_i32, [_u32, _vp, _u32, _u64, _i32, _u64, _u32, _i32, _vp, _vp, _vp]),
+    "pba_workspace_bytes": (_sz, [_u64, _u32, _u32]),
+    "pba_generate": (_i32, [_u64, _u32, _u32, _dbl, _vp, _vp, _u64, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
+    "edges_to_csr_workspace_bytes": (_sz, [_u64, _u64, _i32, _u32]),
+    "edges_to_csr": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libsfgen.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() or python -m paper_1003_3684_amd.build")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        if not hasattr(lib, name):
+            continue
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != SFG_OK:
+        raise SfgenError(rc, load().sfg_last_error().decode())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _idtype(id_bytes):
+    if id_bytes == 4:
+        return torch.int32
+    if id_bytes == 8:
+        return torch.int64
+    raise ValueError("id_bytes must be 4 or 8")
+
+
+def _require_cuda():
+    if not torch.cuda.is_available():
+        raise RuntimeError("sfgen needs a HIP device; no CPU path exists")
+
+
+def workspace(nbytes, device="cuda"):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def device_error(stream=None):
+    code = _u32(0)
+    _check(load().sfg_device_error(_stream(stream), C.byref(code)))
+    return int(code.value)
+
+
+# ----------------------------------------------------------------------------- Kronecker
+def kron_generate(n0, initiator, k, num_edges, *, mode=KRON_SAMPLE, seed=0, graph_id=0, id_bytes=4,
+                  src=None, dst=None, stream=None):
+    """Kronecker edges into device tensors (allocated if not given)."""
+    _require_cuda()
+    lib = load()
+    W = torch.as_tensor(initiator, dtype=torch.float32).contiguous().reshape(-1)
+    if W.numel() != n0 * n0:
+        raise ValueError("initiator must have n0*n0 entries")
+    dt = _idtype(id_bytes)
+    if src is None:
+        src = torch.empty(num_edges, dtype=dt, device="cuda")
+    if dst is None:
+        dst = torch.empty(num_edges, dtype=dt, device="cuda")
+    _check(lib.kron_generate(n0, C.c_void_p(W.data_ptr()), k, num_edges, mode, seed, graph_id, id_bytes,
+                             _ptr(src), _ptr(dst), _stream(stream)))
+    return src, dst
+
+
+# ----------------------------------------------------------------------------- PBA
+def pba_workspace_bytes(n, m, num_parts):
+    return int(load().pba_workspace_bytes(n, m, num_parts))
+
+
+def pba_generate(n, m, num_parts, p_inter, *, seed=0, graph_id=0, faction_off=None, faction_members=None,
+                 id_bytes=4, src=None, dst=None, ws=None, stream=None):
+    """Parallel Barabasi-Albert edges into device tensors."""
+    _require_cuda()
+    lib = load()
+    dt = _idtype(id_bytes)
+    E = n * m
+    if src is None:
+        src = torch.empty(E, dtype=dt, device="cuda")
+    if dst is None:
+        dst = torch.empty(E, dtype=dt, device="cuda")
+    need = pba_workspace_bytes(n, m, num_parts)
+    if ws is None:
+        ws = workspace(need)
+    foff = fmem = None
+    if faction_off is not None:
+        import numpy as np
+        foff = np.ascontiguousarray(faction_off, np.uint32)
+        fmem = np.ascontiguousarray(faction_members if faction_members is not None else [], np.uint32)
+        if fmem.size == 0:
+            fmem = np.zeros(1, np.uint32)
+    _check(lib.pba_generate(n, m, num_parts, float(p_inter),
+                            None if foff is None else foff.ctypes.data_as(_vp),
+                            None if fmem is None else fmem.ctypes.data_as(_vp),
+                            seed, graph_id, id_bytes, _ptr(src), _ptr(dst), _ptr(ws), ws.numel(), _stream(stream)))
+    return src, dst
+
+
+# ----------------------------------------------------------------------------- CSR
+def edges_to_csr_workspace_bytes(n, num_edges, id_bytes, flags):
+    return int(load().edges_to_csr_workspace_bytes(n, num_edges, id_bytes, flags))
+
+
+def edges_to_csr(n, src, dst, *, flags=0, want_hist=True, want_dups=True, row_ptr=None, col=None, ws=None,
+                 stream=None):
+    """CSR of (src, dst): returns (row_ptr, col, hist32 or None, dups tensor or None)."""
+    _require_cuda()
+    lib = load()
+    assert src.dtype == dst.dtype and src.numel() == dst.numel()
+    id_bytes = src.element_size()
+    E = src.numel()
+    N = 2 * E if flags & CSR_SYMMETRIZE else E
+    if row_ptr is None:
+        row_ptr = torch.empty(n + 1, dtype=torch.int64, device=src.device)
+    if col is None:
+        col = torch.empty(max(N, 1), dtype=src.dtype, device=src.device)
+    hist = torch.empty(32, dtype=torch.int64, device=src.device) if want_hist else None
+    dups = torch.empty(1, dtype=torch.int64, device=src.device) if want_dups else None
+    need = edges_to_csr_workspace_bytes(n, E, id_bytes, flags)
+    if ws is None:
+        ws = workspace(need, src.device)
+    _check(lib.edges_to_csr(n, E, _ptr(src), _ptr(dst), id_bytes, flags, _ptr(row_ptr), _ptr(col), _ptr(hist),
+                            _ptr(dups), _ptr(ws), ws.numel(), _stream(stream)))
+    return row_ptr, col, hist, dups
