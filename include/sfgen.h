@@ -131,14 +131,17 @@ int kron_generate(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_
  *                  num_parts); the list of q is the concatenation of the
  *                  members of q's factions, with repetition.
  * src, dst:        device, n*m ids each.
- * workspace:       device, at least pba_workspace_bytes(n, m, num_parts) bytes,
- *                  256-byte aligned.
- * Errors: EINVAL (m == 0, num_parts == 0 or > 8192, n < 2*num_parts,
+ * workspace:       device, at least pba_workspace_bytes(n, m, num_parts,
+ *                  faction_off ? faction_off[num_parts] : 0) bytes, 256-byte
+ *                  aligned.  Custom faction tables are copied into it
+ *                  (the call waits for that copy before returning).
+ * Errors: EINVAL (m == 0, num_parts == 0 or > 4096, n < 2*num_parts,
  * p_inter outside [0,1] or NaN, bad faction table, NULL buffers, graph_id >=
- * 2^24); ERANGE (n*m or n-1 do not fit, a partition holds >= 2^31 slots);
- * ENOSPACE.
+ * 2^24); ERANGE (n*m or n-1 do not fit, a partition holds >= 2^31 slots,
+ * n*m*ceil(n/P) >= 2^64); ENOSPACE.  A partition that receives >= 2^31
+ * requests is detected on the device (sfg_device_error).
  * ---------------------------------------------------------------------- */
-size_t pba_workspace_bytes(uint64_t n, uint32_t m, uint32_t num_parts);
+size_t pba_workspace_bytes(uint64_t n, uint32_t m, uint32_t num_parts, uint64_t num_faction_members);
 int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p_inter, const uint32_t *faction_off,
                  const uint32_t *faction_members, uint64_t seed, uint32_t graph_id, int id_bytes, void *src,
                  void *dst, void *workspace, size_t workspace_bytes, void *stream);

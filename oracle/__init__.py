@@ -51,7 +51,7 @@ def _load():
         "orc_pba_generate": (C.c_int, [C.c_uint64, C.c_uint32, C.c_uint32, C.c_double, C.c_void_p,
                                        C.c_void_p, C.c_uint64, C.c_uint32, i64p, i64p, C.c_void_p,
                                        C.c_void_p, C.c_void_p]),
-        "orc_edges_to_csr": (C.c_int, [C.c_uint64, C.c_uint64, i64p, i64p, C.c_int, u64p, i64p, u64p]),
+        "orc_edges_to_csr": (C.c_int64, [C.c_uint64, C.c_uint64, i64p, i64p, C.c_int, u64p, i64p, u64p]),
         "orc_degree_histogram": (C.c_int, [C.c_uint64, C.c_uint64, i64p, i64p, u64p, u64p]),
         "orc_gamma_mle": (C.c_double, [C.c_uint64, u64p, C.c_uint64]),
         "orc_simple_csr": (C.c_int64, [C.c_uint64, C.c_uint64, i64p, i64p, u64p, i64p]),
@@ -178,7 +178,8 @@ def pba_generate(n, m, P, p, seed, graph_id=0, faction_off=None, faction_members
 
 
 # --------------------------------------------------------------------- CSR and stats
-def edges_to_csr(n, src, dst, symmetrize=False):
+def edges_to_csr(n, src, dst, symmetrize=False, simple=False):
+    """(row_ptr, col, dups) of the sorted entry list; see orc_edges_to_csr."""
     src = np.ascontiguousarray(src, np.int64)
     dst = np.ascontiguousarray(dst, np.int64)
     E = src.size
@@ -186,8 +187,10 @@ def edges_to_csr(n, src, dst, symmetrize=False):
     row_ptr = np.zeros(n + 1, np.uint64)
     col = np.zeros(max(N, 1), np.int64)
     dups = np.zeros(1, np.uint64)
-    _load().orc_edges_to_csr(n, E, src, dst, int(bool(symmetrize)), row_ptr, col, dups)
-    return row_ptr, col[:N], int(dups[0])
+    kept = _load().orc_edges_to_csr(n, E, src, dst, int(bool(symmetrize)) | (2 if simple else 0), row_ptr, col, dups)
+    if kept < 0:
+        raise MemoryError("oracle CSR failed")
+    return row_ptr, col[:kept], int(dups[0])
 
 
 def degree_histogram(n, src, dst):

@@ -375,10 +375,13 @@ done:
 }
 
 /* ---------------------------------------------------------------------------
- * Compressed sparse rows: the edges sorted ascending by (src, dst);
- * row_ptr[v] = number of entries with src < v; col = dst in sorted order.
- * With symmetrize, (v, u) is added for every (u, v) (a self-loop twice).
- * dups = number of positions whose (src, dst) equals the previous one.
+ * Compressed sparse rows: the entries sorted ascending by (row, column);
+ * row_ptr[v] = number of kept entries with row < v; col = their columns in
+ * sorted order.  flags & 1 (symmetrize): (v, u) is added for every (u, v), so
+ * a self-loop appears twice.  flags & 2 (simple): self-loops are dropped and
+ * an entry equal to the previous sorted entry is dropped.  dups = number of
+ * sorted positions whose entry equals the previous one (counted before any
+ * dropping).  Returns the number of kept entries, or -1.
  * ------------------------------------------------------------------------- */
 static int cmp_pair(const void *a, const void *b)
 {
@@ -388,9 +391,10 @@ static int cmp_pair(const void *a, const void *b)
     return 0;
 }
 
-int orc_edges_to_csr(uint64_t n, uint64_t E, const int64_t *src, const int64_t *dst, int symmetrize,
-                     uint64_t *row_ptr, int64_t *col, uint64_t *dups)
+int64_t orc_edges_to_csr(uint64_t n, uint64_t E, const int64_t *src, const int64_t *dst, int flags,
+                         uint64_t *row_ptr, int64_t *col, uint64_t *dups)
 {
+    int symmetrize = flags & 1, simple = flags & 2;
     uint64_t N = symmetrize ? 2 * E : E;
     int64_t *pairs = (int64_t *)malloc(sizeof(int64_t) * 2 * (N ? N : 1));
     if (!pairs) return -1;
@@ -404,16 +408,18 @@ int orc_edges_to_csr(uint64_t n, uint64_t E, const int64_t *src, const int64_t *
     }
     qsort(pairs, N, 2 * sizeof(int64_t), cmp_pair);
     for (uint64_t v = 0; v <= n; ++v) row_ptr[v] = 0;
-    for (uint64_t i = 0; i < N; ++i) row_ptr[pairs[2 * i] + 1] += 1;
-    for (uint64_t v = 0; v < n; ++v) row_ptr[v + 1] += row_ptr[v];
-    uint64_t d = 0;
+    uint64_t d = 0, kept = 0;
     for (uint64_t i = 0; i < N; ++i) {
-        col[i] = pairs[2 * i + 1];
-        if (i > 0 && pairs[2 * i] == pairs[2 * i - 2] && pairs[2 * i + 1] == pairs[2 * i - 1]) ++d;
+        int repeat = i > 0 && pairs[2 * i] == pairs[2 * i - 2] && pairs[2 * i + 1] == pairs[2 * i - 1];
+        if (repeat) ++d;
+        if (simple && (repeat || pairs[2 * i] == pairs[2 * i + 1])) continue;
+        row_ptr[pairs[2 * i] + 1] += 1;
+        col[kept++] = pairs[2 * i + 1];
     }
+    for (uint64_t v = 0; v < n; ++v) row_ptr[v + 1] += row_ptr[v];
     *dups = d;
     free(pairs);
-    return 0;
+    return (int64_t)kept;
 }
 
 /* Degree of every vertex counting both endpoints of every edge (a self-loop

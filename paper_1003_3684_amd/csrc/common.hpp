@@ -21,9 +21,11 @@ enum : uint32_t { TAG_KRON = 1, TAG_PBA1 = 2, TAG_PBA2 = 3, TAG_WEDGE = 4 };
 // Device address of the error word that kernels set when a bounded wait runs
 // out (one word per device, defined in runtime.hip).
 uint32_t *device_error_word();
-enum : uint32_t { DEVERR_LOOKBACK = 1u, DEVERR_QUEUE = 2u };
+enum : uint32_t { DEVERR_LOOKBACK = 1u, DEVERR_QUEUE = 2u, DEVERR_CHAIN = 4u };
 
-constexpr uint32_t kSpinLimit = 1u << 26;
+// Bound of every inter-workgroup wait (iterations of a short sleep), about
+// tens of milliseconds; a wait that runs out records a device error.
+constexpr uint32_t kSpinLimit = 1u << 20;
 
 // Round up to a multiple of 256 bytes (workspace carving granularity).
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }

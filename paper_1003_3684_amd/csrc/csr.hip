@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
                 uint64_t v = load_agent(pj);
                 uint32_t spins = 0;
                 while ((uint32_t)(v >> 58) != a.tag) {
-                    if (++spins > kSpinLimit) {
+                    if (++spins > kSpinLimit || ((spins & 1023) == 0 && load_agent(a.err) != 0)) {
                         raise_device_error(a.err, DEVERR_LOOKBACK);
                         break;
                     }
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
                     uint64_t v = load_agent(a.status + j);
                     uint32_t spins = 0;
                     while ((uint32_t)(v >> 58) != 1u) {
-                        if (++spins > kSpinLimit) {
+                        if (++spins > kSpinLimit || ((spins & 1023) == 0 && load_agent(a.err) != 0)) {
                             raise_device_error(a.err, DEVERR_LOOKBACK);
                             break;
                         }

@@ -36,7 +36,7 @@ SIGNATURES = {
     "sfg_abi_version": (_i32, []),
     "sfg_device_error": (_i32, [_vp, C.POINTER(_u32)]),
     "kron_generate": (_i32, [_u32, _vp, _u32, _u64, _i32, _u64, _u32, _i32, _vp, _vp, _vp]),
-    "pba_workspace_bytes": (_sz, [_u64, _u32, _u32]),
+    "pba_workspace_bytes": (_sz, [_u64, _u32, _u32, _u64]),
     "pba_generate": (_i32, [_u64, _u32, _u32, _dbl, _vp, _vp, _u64, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "edges_to_csr_workspace_bytes": (_sz, [_u64, _u64, _i32, _u32]),
     "edges_to_csr": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -118,8 +118,8 @@ def kron_generate(n0, initiator, k, num_edges, *, mode=KRON_SAMPLE, seed=0, grap
 
 
 # ----------------------------------------------------------------------------- PBA
-def pba_workspace_bytes(n, m, num_parts):
-    return int(load().pba_workspace_bytes(n, m, num_parts))
+def pba_workspace_bytes(n, m, num_parts, num_faction_members=0):
+    return int(load().pba_workspace_bytes(n, m, num_parts, num_faction_members))
 
 
 def pba_generate(n, m, num_parts, p_inter, *, seed=0, graph_id=0, faction_off=None, faction_members=None,
@@ -133,16 +133,18 @@ def pba_generate(n, m, num_parts, p_inter, *, seed=0, graph_id=0, faction_off=No
         src = torch.empty(E, dtype=dt, device="cuda")
     if dst is None:
         dst = torch.empty(E, dtype=dt, device="cuda")
-    need = pba_workspace_bytes(n, m, num_parts)
-    if ws is None:
-        ws = workspace(need)
     foff = fmem = None
+    nmem = 0
     if faction_off is not None:
         import numpy as np
         foff = np.ascontiguousarray(faction_off, np.uint32)
+        nmem = int(foff[-1])
         fmem = np.ascontiguousarray(faction_members if faction_members is not None else [], np.uint32)
         if fmem.size == 0:
             fmem = np.zeros(1, np.uint32)
+    need = pba_workspace_bytes(n, m, num_parts, nmem)
+    if ws is None:
+        ws = workspace(need)
     _check(lib.pba_generate(n, m, num_parts, float(p_inter),
                             None if foff is None else foff.ctypes.data_as(_vp),
                             None if fmem is None else fmem.ctypes.data_as(_vp),

@@ -1,0 +1,87 @@
+"""GPU parity of pba_generate against the oracle (bit-exact edge lists)."""
+import numpy as np
+import pytest
+
+from paper_1003_3684_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(sfg, c):
+    import torch
+    src, dst = sfg.pba_generate(c["n"], c["m"], c["num_parts"], c["p_inter"], seed=c["seed"],
+                                graph_id=c.get("graph_id", 0), faction_off=c.get("faction_off"),
+                                faction_members=c.get("faction_members"), id_bytes=c.get("id_bytes", 4))
+    torch.cuda.synchronize()
+    assert sfg.device_error() == 0
+    return src, dst
+
+
+def _oracle(orc, c):
+    return orc.pba_generate(c["n"], c["m"], c["num_parts"], c["p_inter"], c["seed"], c.get("graph_id", 0),
+                            c.get("faction_off"), c.get("faction_members"))
+
+
+def _compare(sfg, orc, c):
+    src, dst = _gpu(sfg, c)
+    os_, od = _oracle(orc, c)
+    np.testing.assert_array_equal(src.cpu().numpy().astype(np.int64), os_)
+    np.testing.assert_array_equal(dst.cpu().numpy().astype(np.int64), od)
+
+
+def test_pba_small_config(sfg, orc):
+    """65,536 vertices, m = 4, 64 partitions, p = 0.1: every edge equals the oracle's."""
+    _compare(sfg, orc, wl.PBA_SMALL)
+
+
+@pytest.mark.parametrize("p", [0.0, 0.3, 1.0])
+def test_pba_small_config_p(sfg, orc, p):
+    c = dict(wl.PBA_SMALL, p_inter=p, id_bytes=8)
+    _compare(sfg, orc, c)
+
+
+@pytest.mark.parametrize("trial", range(20))
+def test_pba_random(sfg, orc, trial):
+    rng = np.random.default_rng(2000 + trial)
+    c = wl.random_pba_case(rng)
+    c["graph_id"] = int(rng.integers(0, 1 << 24))
+    if trial % 4 == 0:
+        c["id_bytes"] = 8
+    _compare(sfg, orc, c)
+
+
+def test_pba_uneven_partitions(sfg, orc):
+    """n not divisible by P: partitions differ in size by one vertex."""
+    for n, P, m in [(1001, 7, 3), (130, 64, 1), (5000, 3, 5), (4097, 1, 2)]:
+        _compare(sfg, orc, dict(n=n, m=m, num_parts=P, p_inter=0.2, seed=n * 31 + P))
+
+
+def test_pba_fig1_factions(sfg, orc):
+    """The faction structure of the paper's Fig. 1 example on 4 partitions."""
+    # F(0) = F0 + F2 = [1, 2, 0, 1]; the other lists are arbitrary valid ones
+    off = np.array([0, 4, 6, 7, 9], np.uint32)
+    mem = np.array([1, 2, 0, 1, 1, 3, 2, 0, 3], np.uint32)
+    for p in (0.0, 0.25):
+        _compare(sfg, orc, dict(n=20, m=2, num_parts=4, p_inter=p, seed=3, faction_off=off, faction_members=mem))
+        _compare(sfg, orc, dict(n=4000, m=2, num_parts=4, p_inter=p, seed=4, faction_off=off,
+                                faction_members=mem))
+
+
+def test_pba_many_partitions(sfg, orc):
+    """Up to the 4096-partition limit."""
+    _compare(sfg, orc, dict(n=3 * 4096 + 5, m=2, num_parts=4096, p_inter=0.5, seed=9))
+    _compare(sfg, orc, dict(n=2 * 1024, m=3, num_parts=1024, p_inter=0.05, seed=10))
+
+
+@pytest.mark.parametrize("cfg", wl.PBA_SCALE, ids=[c["name"] for c in wl.PBA_SCALE])
+def test_pba_scale_full(sfg, orc, cfg):
+    """2^27 vertices, m = 5, 1,024 partitions: all 671 M edges equal the oracle's."""
+    import torch
+    src, dst = _gpu(sfg, cfg)
+    os_, od = _oracle(orc, cfg)
+    chunk = 1 << 26
+    for s in range(0, os_.size, chunk):
+        np.testing.assert_array_equal(src[s:s + chunk].cpu().numpy().astype(np.int64), os_[s:s + chunk])
+        np.testing.assert_array_equal(dst[s:s + chunk].cpu().numpy().astype(np.int64), od[s:s + chunk])
+    del src, dst
+    torch.cuda.empty_cache()
