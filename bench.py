@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Benchmark of the scale-free graph generation hot path on one MI355X.
+
+A step is one pass of the hot path over the 1-billion-vertex-scale Kronecker
+workload: sample 5 x 2^30 edges from a 3x3 initiator zero-padded to 4x4 with
+15 levels (2^30 vertex ids, int64 endpoints, ~80 GB edge list), then sort them
+into compressed sparse rows with the repeated-edge count and the 32-bin degree
+histogram.  Inputs are synthetic and produced on the GPU by the generator
+itself; every buffer is resident in HBM before the timed region starts.
+
+One JSON line is printed.  Besides the headline edges/s it carries the
+roofline of the dominant kernel (the radix-sort pass), the CPU oracle timed
+on a bounded sample of the same workload, the PBA workload (2^27 vertices,
+m = 5, 1,024 partitions) and the batched-versus-plain ensemble rate when the
+ensemble entry point is built.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("csr.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1003_3684_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profile(kernel_hash):
+    """HBM bytes per radix-pass launch from the committed rocprofv3 counter
+    summary, or None if it was taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", "radix_pass_kron_scale_counters.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != kernel_hash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _cpu_baseline(cfg, sample_edges):
+    """The oracle on the first `sample_edges` edges of the workload: sampling
+    plus CSR of that sample, single-threaded; scaled to edges/s."""
+    import oracle
+    t0 = time.perf_counter()
+    src, dst = oracle.kron_sample(cfg["n0"], cfg["initiator"], cfg["k"], sample_edges, cfg["seed"])
+    t1 = time.perf_counter()
+    n = cfg["n0"] ** cfg["k"]
+    oracle.edges_to_csr(n, src, dst)
+    oracle.degree_histogram(n, src, dst)
+    t2 = time.perf_counter()
+    return {"value": sample_edges / (t2 - t0), "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample_edges} edges of the workload: oracle Kronecker sampling ({t1 - t0:.1f} s) "
+                      f"+ CSR sort and degree histogram ({t2 - t1:.1f} s), single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="edges in the CPU-oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the PBA and ensemble extras")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design note, "
+              "not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1003_3684_amd import native as sfg
+    from paper_1003_3684_amd import workloads as wl
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    sfg.load()
+    cfg = wl.KRON_SCALE
+    n0, W, k, E, seed = cfg["n0"], cfg["initiator"], cfg["k"], cfg["num_edges"], cfg["seed"]
+    n = n0 ** k
+    flags = 0  # directed CSR
+    dt = torch.int64
+    src = torch.empty(E, dtype=dt, device="cuda")
+    dst = torch.empty(E, dtype=dt, device="cuda")
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(E, dtype=dt, device="cuda")
+    hist = torch.empty(32, dtype=torch.int64, device="cuda")
+    dups = torch.empty(1, dtype=torch.int64, device="cuda")
+    ws = sfg.workspace(sfg.edges_to_csr_workspace_bytes(n, E, 8, flags))
+    stream = torch.cuda.current_stream()
+    lib = sfg.load()
+    import ctypes as C
+    Wt = torch.as_tensor(W, dtype=torch.float32).contiguous().reshape(-1)
+    wptr = C.c_void_p(Wt.data_ptr())
+    sptr = C.c_void_p(stream.cuda_stream)
+
+    def step():
+        rc = lib.kron_generate(n0, wptr, k, E, 0, seed, 0, 8, C.c_void_p(src.data_ptr()),
+                               C.c_void_p(dst.data_ptr()), sptr)
+        assert rc == 0, lib.sfg_last_error()
+        rc = lib.edges_to_csr(n, E, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), 8, flags,
+                              C.c_void_p(row_ptr.data_ptr()), C.c_void_p(col.data_ptr()), C.c_void_p(hist.data_ptr()),
+                              C.c_void_p(dups.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(), sptr)
+        assert rc == 0, lib.sfg_last_error()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    assert sfg.device_error() == 0
+    sfg.profile_reset()
+    sfg.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sfg.profile_enable(False)
+    assert sfg.device_error() == 0
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    edges_per_s = E / (ms_per_step / 1e3)
+
+    kernels = {}
+    for name in ("kron_sample", "csr_prepare", "radix_pass", "csr_finish", "csr_rowfill", "degree_hist", "fill",
+                 "csr_digit_bases"):
+        cnt, tot = sfg.profile_query(name)
+        if cnt:
+            kernels[name] = {"launches_per_step": cnt // args.steps, "ms_per_step": tot / args.steps}
+    # Radix pass roofline: pass 0 reads src and dst (16 B) and writes a key
+    # (8 B); every later pass reads and writes one 8-byte key.
+    passes = kernels["radix_pass"]["launches_per_step"]
+    radix_bytes = E * (24 + 16 * (passes - 1))
+    radix_ms = kernels["radix_pass"]["ms_per_step"]
+    achieved = radix_bytes / (radix_ms / 1e3) / 1e9
+    traffic = _traffic_from_profile(_kernel_source_hash())
+    gen_ms = kernels["kron_sample"]["ms_per_step"]
+    total_kernel_ms = sum(v["ms_per_step"] for v in kernels.values())
+    result = {
+        "metric": "edges/s + achieved HBM GB/s at 1B-vertex scale; batched vs plain graphs/s",
+        "value": edges_per_s,
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic (generated on the GPU by the Kronecker sampler, seed 13)",
+        "config": {"workload": cfg["name"], "generator": "kronecker-sample", "n0": n0, "levels": k,
+                   "vertices": n, "edges": E, "id_bytes": 8, "csr": "directed, duplicate count, degree histogram",
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "radix_pass",
+                     "algorithmic_bytes_per_step": radix_bytes, "launches_per_step": passes},
+        "kernels": kernels,
+        "generation": {"edges_per_s": E / (gen_ms / 1e3), "write_GBs": 16 * E / (gen_ms / 1e3) / 1e9,
+                       "bound": "alu"},
+        "csr_edges_per_s": E / ((total_kernel_ms - gen_ms) / 1e3),
+    }
+    del src, dst, row_ptr, col, ws
+    torch.cuda.empty_cache()
+
+    if not args.no_extras:
+        result["extras"] = {"pba": _bench_pba(sfg, wl, torch)}
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_sample)
+    print(json.dumps(result), flush=True)
+
+
+def _bench_pba(sfg, wl, torch, reps=3):
+    """PBA at 2^27 vertices, m = 5, 1,024 partitions, p = 0.1: generation plus
+    the symmetrized CSR with degree histogram."""
+    c = wl.PBA_SCALE[1]
+    E = c["n"] * c["m"]
+    src = torch.empty(E, dtype=torch.int32, device="cuda")
+    dst = torch.empty(E, dtype=torch.int32, device="cuda")
+    ws = sfg.workspace(max(sfg.pba_workspace_bytes(c["n"], c["m"], c["num_parts"]),
+                           sfg.edges_to_csr_workspace_bytes(c["n"], E, 4, sfg.CSR_SYMMETRIZE)))
+    rp = torch.empty(c["n"] + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(2 * E, dtype=torch.int32, device="cuda")
+
+    def gen():
+        sfg.pba_generate(c["n"], c["m"], c["num_parts"], c["p_inter"], seed=c["seed"], src=src, dst=dst, ws=ws)
+
+    def csr():
+        sfg.edges_to_csr(c["n"], src, dst, flags=sfg.CSR_SYMMETRIZE, row_ptr=rp, col=col, ws=ws)
+
+    gen()
+    csr()
+    torch.cuda.synchronize()
+    a, b, d = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    a.record()
+    for _ in range(reps):
+        gen()
+    b.record()
+    for _ in range(reps):
+        csr()
+    d.record()
+    torch.cuda.synchronize()
+    gen_ms, csr_ms = a.elapsed_time(b) / reps, b.elapsed_time(d) / reps
+    out = {"workload": c["name"], "edges": E, "gen_ms": gen_ms, "gen_edges_per_s": E / (gen_ms / 1e3),
+           "csr_ms": csr_ms, "step_edges_per_s": E / ((gen_ms + csr_ms) / 1e3)}
+    del src, dst, ws, rp, col
+    torch.cuda.empty_cache()
+    return out
+
+
+if __name__ == "__main__":
+    main()

@@ -72,6 +72,18 @@ int sfg_abi_version(void);
  * word.  Returns SFG_OK and stores the word in *code. */
 int sfg_device_error(void *stream, uint32_t *code);
 
+/* Launch timing.  While enabled, every kernel launch of the library is
+ * bracketed by a pair of hipEvents recorded on its stream.
+ * sfg_profile_query waits for the recorded launches of the kernel called
+ * `name` and returns how many there were and their summed duration in
+ * milliseconds; sfg_profile_reset forgets all records.  Kernel names:
+ * "kron_sample", "kron_enumerate", "csr_prepare", "radix_pass",
+ * "csr_finish", "csr_rowfill", "degree_hist", "pba_draw1", "pba_resolve",
+ * "pba_count", "pba_scan", "pba_draw2", "pba_substitute". */
+int sfg_profile_enable(int on);
+int sfg_profile_reset(void);
+int sfg_profile_query(const char *name, uint64_t *launches, double *total_ms);
+
 /* ------------------------------------------------------------------------
  * kron_generate -- Kronecker graph edges (section "Parallel Kronecker (PK)
  * method": Kronecker product of adjacency matrices, Fig. 2).
@@ -129,7 +141,8 @@ int kron_generate(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_
  *                  the default F(q) = [q].
  * faction_members: host, faction_off[num_parts] partition ids (each <
  *                  num_parts); the list of q is the concatenation of the
- *                  members of q's factions, with repetition.
+ *                  members of q's factions, with repetition, and must not
+ *                  be empty (slot 0 has no earlier slot to copy).
  * src, dst:        device, n*m ids each.
  * workspace:       device, at least pba_workspace_bytes(n, m, num_parts,
  *                  faction_off ? faction_off[num_parts] : 0) bytes, 256-byte

@@ -171,7 +171,7 @@ def pba_generate(n, m, P, p, seed, graph_id=0, faction_off=None, faction_members
     rc = _load().orc_pba_generate(n, m, P, p, _ptr(foff), _ptr(fmem), seed, graph_id, src, dst,
                                   _ptr(labels), _ptr(counts), _ptr(S))
     if rc != 0:
-        raise MemoryError("oracle PBA failed")
+        raise ValueError("oracle PBA failed (empty faction list or out of memory)")
     if extras:
         return src[:E], dst[:E], labels[:E], counts.reshape(P, P), S[:E]
     return src[:E], dst[:E]

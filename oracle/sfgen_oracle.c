@@ -320,6 +320,11 @@ int orc_pba_generate(uint64_t n, uint32_t m, uint32_t P, double p, const uint32_
     uint8_t *inF = (uint8_t *)malloc(P);
     int rc = -1;
     if (!start || !label || !cnt || !D || !S_base || !off || !S || !NF || !inF) goto done;
+    /* Every processor draws from at least one faction: slot 0 has nothing
+     * earlier to copy. */
+    if (foff)
+        for (uint32_t q = 0; q < P; ++q)
+            if (foff[q + 1] <= foff[q]) goto done;
     for (uint32_t q = 0; q <= P; ++q) start[q] = part_start(n, P, q);
 
     /* Phase 1, every partition. */

@@ -15,6 +15,17 @@ int check_launch(const char *what);
 hipStream_t as_stream(void *s);
 int device_cu_count();
 
+// Launch timing: while profiling is enabled (sfg_profile_enable), a
+// ProfScope around a kernel launch records a pair of hipEvents on the launch
+// stream, and sfg_profile_query sums their durations per kernel name.
+struct ProfScope {
+    ProfScope(const char *name, hipStream_t s);
+    ~ProfScope();
+    int slot = -1;
+    hipStream_t stream;
+    const char *kname;
+};
+
 // Counter-word tags of the Philox streams.
 enum : uint32_t { TAG_KRON = 1, TAG_PBA1 = 2, TAG_PBA2 = 3, TAG_WEDGE = 4 };
 

@@ -1,8 +1,9 @@
 // Edge list -> compressed sparse rows, and the degree histogram.
 //
-// Entries (src, dst) are packed into one unsigned key (src << wb) | dst, with
-// wb = bits(n - 1), and sorted by a least-significant-digit radix sort with
-// 8-bit digits over the 2 * wb live bits.  Each digit pass is a single
+// Entries (src, dst) are packed into one unsigned key (src << db) | dst, with
+// db = bits(n - 1) (rounded up to a whole digit when in-degrees are needed),
+// and sorted by a least-significant-digit radix sort with 8-bit digits over
+// the live key bits.  Each digit pass is a single
 // "onesweep" kernel: a workgroup takes the next tile by an atomic ticket,
 // ranks its keys stably in LDS, publishes its per-digit counts and finds the
 // counts of all earlier tiles by decoupled look-back, then writes its keys
@@ -15,7 +16,11 @@
 // with SIMPLE it also drops self-loops and repeats, compacting by a
 // look-back scan.  Rows with no entry are filled by a reverse min-scan over
 // the row starts.  The degree histogram counts deg(v) = out + in per vertex
-// (the degree distributions of the paper's Results section).
+// (the degree distributions of the paper's Results section).  For a directed
+// CSR the in-degrees come from the sort itself: once the digit passes over
+// the destination field are done the keys are ordered by destination, and the
+// next pass marks where each destination's run starts (a column-start array
+// filled like the row starts) -- no atomics.
 #include <string.h>
 
 #include <algorithm>
@@ -94,8 +99,7 @@ struct PrepArgs {
     uint64_t E, N;
     const void *src, *dst;
     uint64_t *ghist;   // [passes][256]
-    uint32_t *indeg;   // in-degree counters (directed histogram) or null
-    int wb, passes;
+    int wb, passes;    // wb: width of the destination field
 };
 
 template <typename IdT, typename KeyT, bool SYM>
@@ -108,7 +112,6 @@ __global__ __launch_bounds__(256) void csr_prepare(PrepArgs a) {
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < a.N; i += stride) {
         const KeyT k = entry_key<IdT, KeyT, SYM>(src, dst, a.E, i, a.wb);
         for (int p = 0; p < a.passes; ++p) atomicAdd(&s_h[p * kRadix + (uint32_t)((k >> (8 * p)) & 255)], 1u);
-        if (a.indeg && i < a.E) atomicAdd(&a.indeg[(uint64_t)dst[i]], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < a.passes * kRadix; i += 256)
@@ -139,11 +142,14 @@ struct PassArgs {
     const uint64_t *gbase;  // [256] of this pass
     uint32_t *ticket;
     uint32_t *err;
-    int wb, shift;
+    uint64_t *csc;          // column starts (BOUND passes only)
+    int wb, shift;          // wb: width of the destination field
     uint32_t tag;
 };
 
-template <typename IdT, typename KeyT, bool SYM, bool FIRST>
+// BOUND: the input keys are ordered by destination; mark the first position
+// of every destination run in csc.
+template <typename IdT, typename KeyT, bool SYM, bool FIRST, bool BOUND>
 __global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
     __shared__ KeyT s_keys[kPassTile];
     __shared__ uint32_t s_cnt[kPassWaves][kRadix];
@@ -177,6 +183,22 @@ __global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
         } else {
             k[i] = 0;
             d[i] = kRadix;  // no digit
+        }
+    }
+
+    if (BOUND) {
+        // The key before position idx: the previous lane of the same item,
+        // lane 63 of the previous item, or (first key of the wave) memory.
+        const KeyT mask = ((KeyT)1 << a.wb) - 1;
+        const KeyT *in = static_cast<const KeyT *>(a.in);
+        KeyT carry = (wbase > 0 && wbase <= a.N) ? in[wbase - 1] : (KeyT)0;
+#pragma unroll
+        for (int i = 0; i < kPassItems; ++i) {
+            const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
+            KeyT prev = __shfl_up(k[i], 1, 64);
+            if (lane == 0) prev = carry;
+            carry = __shfl(k[i], 63, 64);
+            if (idx < a.N && (idx == 0 || (k[i] & mask) != (prev & mask))) a.csc[(uint64_t)(k[i] & mask)] = idx;
         }
     }
 
@@ -482,7 +504,7 @@ __device__ __forceinline__ int log2_bin(uint64_t d) {
     return b > 31 ? 31 : b;
 }
 
-__global__ __launch_bounds__(256) void degree_hist_kernel(const uint64_t *rp_raw, const uint32_t *indeg, uint64_t n,
+__global__ __launch_bounds__(256) void degree_hist_kernel(const uint64_t *rp_raw, const uint64_t *csc, uint64_t n,
                                                           uint64_t *hist) {
     __shared__ uint32_t s_h[32];
     if (threadIdx.x < 32) s_h[threadIdx.x] = 0;
@@ -490,7 +512,7 @@ __global__ __launch_bounds__(256) void degree_hist_kernel(const uint64_t *rp_raw
     const uint64_t stride = (uint64_t)gridDim.x * 256;
     for (uint64_t v = (uint64_t)blockIdx.x * 256 + threadIdx.x; v < n; v += stride) {
         uint64_t deg = rp_raw[v + 1] - rp_raw[v];
-        if (indeg) deg += indeg[v];
+        if (csc) deg += csc[v + 1] - csc[v];
         atomicAdd(&s_h[log2_bin(deg)], 1u);
     }
     __syncthreads();
@@ -506,7 +528,7 @@ int bits_for(uint64_t n) {  // bits to hold ids in [0, n)
 
 struct Plan {
     uint64_t n, E, N;
-    int wb, kb, passes, key_bytes;
+    int wb, db, kb, passes, key_bytes, dpasses;
     bool sym, simple, hist, directed_hist;
     uint64_t pass_tiles, fin_tiles, chunks;
     // workspace carving
@@ -523,11 +545,15 @@ Plan make_plan(uint64_t n, uint64_t E, int id_bytes, uint32_t flags, bool want_h
     p.simple = flags & SFG_CSR_SIMPLE;
     p.N = p.sym ? 2 * E : E;
     p.wb = bits_for(n);
-    p.kb = 2 * p.wb;
-    p.passes = (p.kb + 7) / 8;
-    p.key_bytes = p.kb <= 32 ? 4 : 8;
     p.hist = want_hist;
     p.directed_hist = want_hist && !p.sym;
+    // With in-degrees wanted, the destination field fills whole digits so
+    // that some pass boundary leaves the keys ordered by destination.
+    p.db = p.directed_hist ? 8 * ((p.wb + 7) / 8) : p.wb;
+    p.dpasses = p.db / 8;
+    p.kb = p.wb + p.db;
+    p.passes = (p.kb + 7) / 8;
+    p.key_bytes = p.kb <= 32 ? 4 : 8;
     p.pass_tiles = (p.N + kPassTile - 1) / kPassTile;
     p.fin_tiles = (p.N + kFinTile - 1) / kFinTile;
     p.chunks = (n + 1 + kScanChunk - 1) / kScanChunk;
@@ -543,7 +569,7 @@ Plan make_plan(uint64_t n, uint64_t E, int id_bytes, uint32_t flags, bool want_h
     p.off_ghist = take(8 * kRadix * 8);
     p.off_gbase = take(8 * kRadix * 8);
     p.off_tickets = take(16 * 4);
-    p.off_indeg = take(p.directed_hist ? n * 4 : 0);
+    p.off_indeg = take(p.directed_hist ? (n + 1) * 8 : 0);
     p.off_rpraw = take(want_hist && p.simple ? (n + 1) * 8 : 0);
     p.off_rpc = take(0);
     p.off_cmin = take(std::max<uint64_t>(p.chunks, 1) * 8);
@@ -559,13 +585,16 @@ int fill_grid(uint64_t n) {
 }
 
 template <typename T> void fill(T *p, uint64_t n, T v, hipStream_t s) {
-    if (n) fill_kernel<T><<<fill_grid(n), 256, 0, s>>>(p, n, v);
+    if (n) {
+        ProfScope _ps("fill", s);
+        fill_kernel<T><<<fill_grid(n), 256, 0, s>>>(p, n, v);
+    }
 }
 
 void row_fill(uint64_t *rp, uint64_t n1, uint64_t *cmin, uint64_t chunks, hipStream_t s) {
-    rowfill_reduce<<<(int)chunks, 256, 0, s>>>(rp, n1, cmin);
-    rowfill_chunks<<<1, 1024, 0, s>>>(cmin, chunks);
-    rowfill_apply<<<(int)chunks, 256, 0, s>>>(rp, n1, cmin);
+    { ProfScope _ps("csr_rowfill", s); rowfill_reduce<<<(int)chunks, 256, 0, s>>>(rp, n1, cmin); }
+    { ProfScope _ps("csr_rowfill", s); rowfill_chunks<<<1, 1024, 0, s>>>(cmin, chunks); }
+    { ProfScope _ps("csr_rowfill", s); rowfill_apply<<<(int)chunks, 256, 0, s>>>(rp, n1, cmin); }
 }
 
 template <typename IdT, typename KeyT>
@@ -578,7 +607,7 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
     uint64_t *ghist = reinterpret_cast<uint64_t *>(ws + P.off_ghist);
     uint64_t *gbase = reinterpret_cast<uint64_t *>(ws + P.off_gbase);
     uint32_t *tickets = reinterpret_cast<uint32_t *>(ws + P.off_tickets);
-    uint32_t *indeg = P.directed_hist ? reinterpret_cast<uint32_t *>(ws + P.off_indeg) : nullptr;
+    uint64_t *csc = P.directed_hist ? reinterpret_cast<uint64_t *>(ws + P.off_indeg) : nullptr;
     uint64_t *rp_raw_ws = (P.hist && P.simple) ? reinterpret_cast<uint64_t *>(ws + P.off_rpraw) : nullptr;
     uint64_t *cmin = reinterpret_cast<uint64_t *>(ws + P.off_cmin);
     uint64_t *fstatus = P.simple ? reinterpret_cast<uint64_t *>(ws + P.off_fstatus) : nullptr;
@@ -589,44 +618,49 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
     fill<uint32_t>(tickets, 16, 0, s);
     if (P.N) fill<uint64_t>(status, P.pass_tiles * kRadix, 0, s);
     if (fstatus && P.N) fill<uint64_t>(fstatus, P.fin_tiles, 0, s);
-    if (indeg) fill<uint32_t>(indeg, P.n, 0, s);
+    if (csc) {
+        fill<uint64_t>(csc, P.n, kNoRow, s);
+        fill<uint64_t>(csc + P.n, 1, P.N, s);
+    }
     if (dups) fill<uint64_t>(dups, 1, 0, s);
     if (hist) fill<uint64_t>(hist, 32, 0, s);
     fill<uint64_t>(row_ptr, P.n + 1, kNoRow, s);
     if (rp_raw_ws) fill<uint64_t>(rp_raw_ws, P.n + 1, kNoRow, s);
 
     if (P.N > 0) {
-        PrepArgs pa{P.E, P.N, src, dst, ghist, indeg, P.wb, P.passes};
+        PrepArgs pa{P.E, P.N, src, dst, ghist, P.db, P.passes};
         const int pg = fill_grid(P.N);
         if (P.sym)
-            csr_prepare<IdT, KeyT, true><<<pg, 256, 0, s>>>(pa);
+            { ProfScope _ps("csr_prepare", s); csr_prepare<IdT, KeyT, true><<<pg, 256, 0, s>>>(pa); }
         else
-            csr_prepare<IdT, KeyT, false><<<pg, 256, 0, s>>>(pa);
-        csr_digit_bases<<<P.passes, 256, 0, s>>>(ghist, gbase);
+            { ProfScope _ps("csr_prepare", s); csr_prepare<IdT, KeyT, false><<<pg, 256, 0, s>>>(pa); }
+        { ProfScope _ps("csr_digit_bases", s); csr_digit_bases<<<P.passes, 256, 0, s>>>(ghist, gbase); }
 
         // Ping-pong so that the last pass lands in keysA.
         for (int p = 0; p < P.passes; ++p) {
             const int remaining = P.passes - 1 - p;  // passes after this one
             KeyT *out = (remaining % 2 == 0) ? keysA : keysB;
             KeyT *in = (remaining % 2 == 0) ? keysB : keysA;
-            PassArgs a{P.E, P.N, src, dst, in, out, status, gbase + p * kRadix, tickets + p, err, P.wb, 8 * p,
+            PassArgs a{P.E, P.N, src, dst, in, out, status, gbase + p * kRadix, tickets + p, err, csc, P.db, 8 * p,
                        (uint32_t)(p + 1)};
             const int g = (int)P.pass_tiles;
-            if (p == 0) {
+            if (csc && p == P.dpasses) {
+                { ProfScope _ps("radix_pass", s); radix_pass<IdT, KeyT, false, false, true><<<g, kPassThreads, 0, s>>>(a); }
+            } else if (p == 0) {
                 if (P.sym)
-                    radix_pass<IdT, KeyT, true, true><<<g, kPassThreads, 0, s>>>(a);
+                    { ProfScope _ps("radix_pass", s); radix_pass<IdT, KeyT, true, true, false><<<g, kPassThreads, 0, s>>>(a); }
                 else
-                    radix_pass<IdT, KeyT, false, true><<<g, kPassThreads, 0, s>>>(a);
+                    { ProfScope _ps("radix_pass", s); radix_pass<IdT, KeyT, false, true, false><<<g, kPassThreads, 0, s>>>(a); }
             } else {
-                radix_pass<IdT, KeyT, false, false><<<g, kPassThreads, 0, s>>>(a);
+                { ProfScope _ps("radix_pass", s); radix_pass<IdT, KeyT, false, false, false><<<g, kPassThreads, 0, s>>>(a); }
             }
         }
         FinArgs fa{P.N, P.n, keysA, col, row_ptr, P.simple ? rp_raw_ws : nullptr, dups, fstatus, tickets + 15, err,
-                   P.wb};
+                   P.db};
         if (P.simple)
-            csr_finish<IdT, KeyT, true><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa);
+            { ProfScope _ps("csr_finish", s); csr_finish<IdT, KeyT, true><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa); }
         else
-            csr_finish<IdT, KeyT, false><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa);
+            { ProfScope _ps("csr_finish", s); csr_finish<IdT, KeyT, false><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa); }
     } else {
         fill<uint64_t>(row_ptr + P.n, 1, 0, s);
         if (rp_raw_ws) fill<uint64_t>(rp_raw_ws + P.n, 1, 0, s);
@@ -638,7 +672,8 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
             row_fill(rp_raw_ws, P.n + 1, cmin, P.chunks, s);
             raw = rp_raw_ws;
         }
-        degree_hist_kernel<<<fill_grid(P.n), 256, 0, s>>>(raw, indeg, P.n, hist);
+        if (csc) row_fill(csc, P.n + 1, cmin, P.chunks, s);
+        { ProfScope _ps("degree_hist", s); degree_hist_kernel<<<fill_grid(P.n), 256, 0, s>>>(raw, csc, P.n, hist); }
     }
     return check_launch("edges_to_csr");
 }
@@ -666,7 +701,8 @@ extern "C" int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, con
     if (num_edges > (1ull << 54)) return fail(SFG_ERANGE, "edges_to_csr: too many edges");
     const bool sym = flags & SFG_CSR_SYMMETRIZE;
     const uint64_t N = sym ? 2 * num_edges : num_edges;
-    if ((N + kPassTile - 1) / kPassTile > 0x7FFFFFFFull) return fail(SFG_ERANGE, "edges_to_csr: too many tiles");
+    // One workgroup per tile: a dispatch's work-item count must stay below 2^32.
+    if (N > (1ull << 36)) return fail(SFG_ERANGE, "edges_to_csr: more than 2^36 entries");
     Plan P = make_plan(n, num_edges, id_bytes, flags, degree_hist32 != nullptr);
     if (P.total > 0 && !workspace) return fail(SFG_EINVAL, "edges_to_csr: workspace is NULL");
     if (workspace_bytes < P.total)

@@ -243,11 +243,11 @@ void launch_fast(const FastArgs &a, uint32_t nt, void *src, void *dst, hipStream
     const int g = grid_for(a.num_edges);
     IdT *S = static_cast<IdT *>(src), *D = static_cast<IdT *>(dst);
     if (nt <= 3)
-        kron_sample_fast<IdT, AccT, POW2, 3><<<g, kBlock, 0, s>>>(a, S, D);
+        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 3><<<g, kBlock, 0, s>>>(a, S, D); }
     else if (nt <= 8)
-        kron_sample_fast<IdT, AccT, POW2, 8><<<g, kBlock, 0, s>>>(a, S, D);
+        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 8><<<g, kBlock, 0, s>>>(a, S, D); }
     else
-        kron_sample_fast<IdT, AccT, POW2, 15><<<g, kBlock, 0, s>>>(a, S, D);
+        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 15><<<g, kBlock, 0, s>>>(a, S, D); }
 }
 
 template <typename IdT, typename AccT>
@@ -307,13 +307,13 @@ extern "C" int kron_generate(uint32_t n0, const float *initiator, uint32_t k, ui
         const int g = grid_for(num_edges);
         const bool idx32 = ne <= (1ull << 32);
         if (id_bytes == 4 && idx32)
-            kron_enumerate_kernel<int32_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst);
+            { ProfScope _ps("kron_enumerate", s); kron_enumerate_kernel<int32_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst); }
         else if (id_bytes == 4)
-            kron_enumerate_kernel<int32_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst);
+            { ProfScope _ps("kron_enumerate", s); kron_enumerate_kernel<int32_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst); }
         else if (idx32)
-            kron_enumerate_kernel<int64_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
+            { ProfScope _ps("kron_enumerate", s); kron_enumerate_kernel<int64_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst); }
         else
-            kron_enumerate_kernel<int64_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
+            { ProfScope _ps("kron_enumerate", s); kron_enumerate_kernel<int64_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst); }
         return check_launch("kron_generate(enumerate)");
     }
 
@@ -358,10 +358,10 @@ extern "C" int kron_generate(uint32_t n0, const float *initiator, uint32_t k, ui
     a.nt = tab.nt;
     const int g = grid_for(num_edges);
     if (id_bytes == 4)
-        kron_sample_general<int32_t, uint32_t><<<g, kBlock, 0, s>>>(a, tab, (int32_t *)src, (int32_t *)dst);
+        { ProfScope _ps("kron_sample", s); kron_sample_general<int32_t, uint32_t><<<g, kBlock, 0, s>>>(a, tab, (int32_t *)src, (int32_t *)dst); }
     else if (acc32)
-        kron_sample_general<int64_t, uint32_t><<<g, kBlock, 0, s>>>(a, tab, (int64_t *)src, (int64_t *)dst);
+        { ProfScope _ps("kron_sample", s); kron_sample_general<int64_t, uint32_t><<<g, kBlock, 0, s>>>(a, tab, (int64_t *)src, (int64_t *)dst); }
     else
-        kron_sample_general<int64_t, uint64_t><<<g, kBlock, 0, s>>>(a, tab, (int64_t *)src, (int64_t *)dst);
+        { ProfScope _ps("kron_sample", s); kron_sample_general<int64_t, uint64_t><<<g, kBlock, 0, s>>>(a, tab, (int64_t *)src, (int64_t *)dst); }
     return check_launch("kron_generate(sample, general)");
 }

@@ -82,8 +82,6 @@ __global__ __launch_bounds__(kDrawThreads) void pba_draw1(Draw1Args a) {
     const uint32_t q = blockIdx.y;
     const uint64_t s0 = part_start(q, a.n, a.P), s1 = part_start(q + 1, a.n, a.P);
     const uint64_t nslots = (s1 - s0) * a.m;
-    const uint64_t j = (uint64_t)blockIdx.x * kDrawThreads + threadIdx.x;
-    if (j >= nslots) return;
     uint32_t s = 1, u = 1, self = q;
     const uint32_t *F = &self, *U = &self;
     if (a.f.foff) {
@@ -92,19 +90,22 @@ __global__ __launch_bounds__(kDrawThreads) void pba_draw1(Draw1Args a) {
         U = a.f.umem + a.f.uoff[q];
         u = a.f.uoff[q + 1] - a.f.uoff[q];
     }
-    uint32_t enc;
-    if (j < s) {
-        enc = kTerm | F[j];
-    } else {
-        const Block4 w = philox((uint32_t)j, (uint32_t)(j >> 32), q, a.tagword, a.key0, a.key1);
-        const uint64_t U64 = make_u64(w.w1, w.w2);
-        const uint32_t nnf = (uint32_t)a.P - u;
-        if (nnf > 0 && (uint64_t)w.w0 < a.thr_p)
-            enc = kTerm | nonfaction((uint32_t)uidx64(U64, nnf), U, u);
-        else
-            enc = (uint32_t)uidx64(U64, j);  // copy an earlier slot
+    const uint32_t nnf = (uint32_t)a.P - u;
+    const uint64_t stride = (uint64_t)gridDim.x * kDrawThreads;
+    for (uint64_t j = (uint64_t)blockIdx.x * kDrawThreads + threadIdx.x; j < nslots; j += stride) {
+        uint32_t enc;
+        if (j < s) {
+            enc = kTerm | F[j];
+        } else {
+            const Block4 w = philox((uint32_t)j, (uint32_t)(j >> 32), q, a.tagword, a.key0, a.key1);
+            const uint64_t U64 = make_u64(w.w1, w.w2);
+            if (nnf > 0 && (uint64_t)w.w0 < a.thr_p)
+                enc = kTerm | nonfaction((uint32_t)uidx64(U64, nnf), U, u);
+            else
+                enc = (uint32_t)uidx64(U64, j);  // copy an earlier slot
+        }
+        a.lab[s0 * a.m + j] = enc;
     }
-    a.lab[s0 * a.m + j] = enc;
 }
 
 // ----------------------------------------------------------------------------- phase 2 draw
@@ -115,9 +116,7 @@ struct Draw2Args {
     uint32_t *sel;
 };
 
-__global__ __launch_bounds__(kDrawThreads) void pba_draw2(Draw2Args a) {
-    const uint64_t g = (uint64_t)blockIdx.x * kDrawThreads + threadIdx.x;
-    if (g >= a.total) return;
+__device__ __forceinline__ void pba_draw2_one(const Draw2Args &a, uint64_t g) {
     // partition l with sbase[l] <= g < sbase[l+1]
     uint32_t lo = 0, hi = (uint32_t)a.P;
     while (hi - lo > 1) {
@@ -145,6 +144,12 @@ __global__ __launch_bounds__(kDrawThreads) void pba_draw2(Draw2Args a) {
         enc = (uint32_t)((r - 3) >> 1);
     }
     a.sel[g] = enc;
+}
+
+__global__ __launch_bounds__(kDrawThreads) void pba_draw2(Draw2Args a) {
+    const uint64_t stride = (uint64_t)gridDim.x * kDrawThreads;
+    for (uint64_t g = (uint64_t)blockIdx.x * kDrawThreads + threadIdx.x; g < a.total; g += stride)
+        pba_draw2_one(a, g);
 }
 
 // ----------------------------------------------------------------------------- chain resolution
@@ -495,8 +500,13 @@ extern "C" int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p
     std::vector<uint32_t> foff, fmem, uoff, umem;
     if (faction_off) {
         if (faction_off[0] != 0) return fail(SFG_EINVAL, "pba_generate: faction_off[0] must be 0");
-        for (uint32_t q = 0; q < P; ++q)
+        for (uint32_t q = 0; q < P; ++q) {
             if (faction_off[q + 1] < faction_off[q]) return fail(SFG_EINVAL, "pba_generate: faction_off is not monotone");
+            // Copying needs an earlier slot: every partition starts from at
+            // least one faction member.
+            if (faction_off[q + 1] == faction_off[q])
+                return fail(SFG_EINVAL, "pba_generate: partition %u has an empty faction list", q);
+        }
         const uint32_t total = faction_off[P];
         if (total > 0 && !faction_members) return fail(SFG_EINVAL, "pba_generate: faction_members is NULL");
         foff.assign(faction_off, faction_off + P + 1);
@@ -552,31 +562,34 @@ extern "C" int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p
     const int res_grid = cus * 8;
 
     // Phase 1.
-    pba_phase1_bases<<<(P + 1 + 255) / 256, 256, 0, s>>>(n, P, m, base1);
+    { ProfScope _ps("pba_tile_table", s); pba_phase1_bases<<<(P + 1 + 255) / 256, 256, 0, s>>>(n, P, m, base1); }
     Draw1Args d1{n, P, m, key0, key1, TAG_PBA1 | (graph_id << 8), 0, fac, lab};
     {
         double t = std::floor(p_inter * 4294967296.0);
         d1.thr_p = t <= 0.0 ? 0 : (t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t);
     }
-    dim3 g1((unsigned)((pl.Lmax * m + kDrawThreads - 1) / kDrawThreads), P);
-    pba_draw1<<<g1, kDrawThreads, 0, s>>>(d1);
-    pba_tile_table<<<1, 64, 0, s>>>(base1, P, pl.xstride, xpre, xtot, queues);
-    pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{lab, base1, xpre, xtot, queues, err, P, pl.xstride});
+    // Grid-stride launches: a dispatch's work-item count per dimension must
+    // stay below 2^32.
+    const uint64_t per_part = (pl.Lmax * m + kDrawThreads - 1) / kDrawThreads;
+    dim3 g1((unsigned)std::min<uint64_t>(per_part, std::max<uint64_t>(1, (uint64_t)cus * 64 / P + 1)), P);
+    { ProfScope _ps("pba_draw1", s); pba_draw1<<<g1, kDrawThreads, 0, s>>>(d1); }
+    { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<1, 64, 0, s>>>(base1, P, pl.xstride, xpre, xtot, queues); }
+    { ProfScope _ps("pba_resolve", s); pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{lab, base1, xpre, xtot, queues, err, P, pl.xstride}); }
 
     // Count exchange.
     dim3 gc(pl.T1, P);
-    pba_count<<<gc, 256, P * 4, s>>>(CountArgs{lab, base1, H, P, pl.T1, pl.CT});
+    { ProfScope _ps("pba_count", s); pba_count<<<gc, 256, P * 4, s>>>(CountArgs{lab, base1, H, P, pl.T1, pl.CT}); }
     dim3 gs((unsigned)pl.groups, (P + 255) / 256);
-    pba_scan_partial<<<gs, 256, 0, s>>>(H, pl.R, P, part);
-    pba_scan_groups<<<(P + 255) / 256, 256, 0, s>>>(part, pl.groups, P, D, err);
-    pba_scan_apply<<<gs, 256, 0, s>>>(H, pl.R, P, part);
-    pba_list_bases<<<1, 1024, 0, s>>>(D, P, sbase);
+    { ProfScope _ps("pba_scan", s); pba_scan_partial<<<gs, 256, 0, s>>>(H, pl.R, P, part); }
+    { ProfScope _ps("pba_scan", s); pba_scan_groups<<<(P + 255) / 256, 256, 0, s>>>(part, pl.groups, P, D, err); }
+    { ProfScope _ps("pba_scan", s); pba_scan_apply<<<gs, 256, 0, s>>>(H, pl.R, P, part); }
+    { ProfScope _ps("pba_scan", s); pba_list_bases<<<1, 1024, 0, s>>>(D, P, sbase); }
 
     // Phase 2.
     Draw2Args d2{n, P, pl.E, key0, key1, TAG_PBA2 | (graph_id << 8), sbase, sel};
-    pba_draw2<<<(unsigned)((pl.E + kDrawThreads - 1) / kDrawThreads), kDrawThreads, 0, s>>>(d2);
-    pba_tile_table<<<1, 64, 0, s>>>(sbase, P, pl.xstride, xpre, xtot, queues + kXcd);
-    pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{sel, sbase, xpre, xtot, queues + kXcd, err, P, pl.xstride});
+    { ProfScope _ps("pba_draw2", s); pba_draw2<<<(unsigned)std::min<uint64_t>((pl.E + kDrawThreads - 1) / kDrawThreads, (uint64_t)cus * 64), kDrawThreads, 0, s>>>(d2); }
+    { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<1, 64, 0, s>>>(sbase, P, pl.xstride, xpre, xtot, queues + kXcd); }
+    { ProfScope _ps("pba_resolve", s); pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{sel, sbase, xpre, xtot, queues + kXcd, err, P, pl.xstride}); }
 
     // Substitution.
     uint32_t lbits = 0;
@@ -584,8 +597,8 @@ extern "C" int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p
     SubArgs sa{n, P, m, pl.T1, pl.CT, lbits, lab, base1, H, sbase, sel, src, dst};
     dim3 gsub(pl.T1, P);
     if (id_bytes == 4)
-        pba_substitute<int32_t><<<gsub, kSubThreads, lds_sub, s>>>(sa);
+        { ProfScope _ps("pba_substitute", s); pba_substitute<int32_t><<<gsub, kSubThreads, lds_sub, s>>>(sa); }
     else
-        pba_substitute<int64_t><<<gsub, kSubThreads, lds_sub, s>>>(sa);
+        { ProfScope _ps("pba_substitute", s); pba_substitute<int64_t><<<gsub, kSubThreads, lds_sub, s>>>(sa); }
     return check_launch("pba_generate");
 }

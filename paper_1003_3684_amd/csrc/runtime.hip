@@ -2,8 +2,12 @@
 // handles, device properties and the device error word.
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
+
+#include <string.h>
 
 #include <mutex>
+#include <vector>
 
 #include "common.hpp"
 
@@ -59,9 +63,93 @@ uint32_t *device_error_word() {
     return addr[dev];
 }
 
+// ----------------------------------------------------------------- launch timing
+namespace {
+struct ProfRecord {
+    const char *name;
+    hipEvent_t start, stop;
+    bool open;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRecord> g_prof;  // events are reused across resets
+size_t g_prof_used = 0;
+}  // namespace
+
+// SFGEN_DEBUG_SYNC=1: synchronise after every launch and report the first
+// kernel after which the device error word is set (diagnostics only).
+static bool debug_sync() {
+    static const bool on = [] {
+        const char *e = getenv("SFGEN_DEBUG_SYNC");
+        return e && e[0] == '1';
+    }();
+    return on;
+}
+
+ProfScope::ProfScope(const char *name, hipStream_t s) : stream(s), kname(name) {
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    if (!g_prof_on) return;
+    if (g_prof_used == g_prof.size()) {
+        ProfRecord r{nullptr, nullptr, nullptr, false};
+        if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
+        g_prof.push_back(r);
+    }
+    slot = (int)g_prof_used++;
+    g_prof[slot].name = name;
+    g_prof[slot].open = true;
+    (void)hipEventRecord(g_prof[slot].start, s);
+}
+
+ProfScope::~ProfScope() {
+    if (debug_sync()) {
+        uint32_t v = 0;
+        uint32_t *w = device_error_word();
+        if (hipStreamSynchronize(stream) != hipSuccess)
+            fprintf(stderr, "sfgen debug: %s: %s\n", kname, hipGetErrorString(hipGetLastError()));
+        else if (w && hipMemcpy(&v, w, sizeof(v), hipMemcpyDeviceToHost) == hipSuccess && v)
+            fprintf(stderr, "sfgen debug: device error word %u after %s\n", v, kname);
+    }
+    if (slot < 0) return;
+    std::lock_guard<std::mutex> lock(g_prof_mu);
+    (void)hipEventRecord(g_prof[slot].stop, stream);
+    g_prof[slot].open = false;
+}
+
 }  // namespace sfg
 
 extern "C" {
+
+int sfg_profile_enable(int on) {
+    std::lock_guard<std::mutex> lock(sfg::g_prof_mu);
+    sfg::g_prof_on = on != 0;
+    return SFG_OK;
+}
+
+int sfg_profile_reset(void) {
+    std::lock_guard<std::mutex> lock(sfg::g_prof_mu);
+    sfg::g_prof_used = 0;
+    return SFG_OK;
+}
+
+int sfg_profile_query(const char *name, uint64_t *launches, double *total_ms) {
+    if (!name || !launches || !total_ms) return sfg::fail(SFG_EINVAL, "sfg_profile_query: NULL argument");
+    std::lock_guard<std::mutex> lock(sfg::g_prof_mu);
+    uint64_t n = 0;
+    double ms = 0.0;
+    for (size_t i = 0; i < sfg::g_prof_used; ++i) {
+        const auto &r = sfg::g_prof[i];
+        if (r.open || strcmp(r.name, name) != 0) continue;
+        if (hipEventSynchronize(r.stop) != hipSuccess) return sfg::check_launch("sfg_profile_query");
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess) return sfg::check_launch("sfg_profile_query");
+        ms += t;
+        ++n;
+    }
+    *launches = n;
+    *total_ms = ms;
+    return SFG_OK;
+}
+
 
 const char *sfg_last_error(void) { return sfg::t_last_error; }
 

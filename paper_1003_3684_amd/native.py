@@ -35,6 +35,9 @@ SIGNATURES = {
     "sfg_last_error": (C.c_char_p, []),
     "sfg_abi_version": (_i32, []),
     "sfg_device_error": (_i32, [_vp, C.POINTER(_u32)]),
+    "sfg_profile_enable": (_i32, [_i32]),
+    "sfg_profile_reset": (_i32, []),
+    "sfg_profile_query": (_i32, [C.c_char_p, C.POINTER(_u64), C.POINTER(C.c_double)]),
     "kron_generate": (_i32, [_u32, _vp, _u32, _u64, _i32, _u64, _u32, _i32, _vp, _vp, _vp]),
     "pba_workspace_bytes": (_sz, [_u64, _u32, _u32, _u64]),
     "pba_generate": (_i32, [_u64, _u32, _u32, _dbl, _vp, _vp, _u64, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
@@ -96,6 +99,21 @@ def device_error(stream=None):
     code = _u32(0)
     _check(load().sfg_device_error(_stream(stream), C.byref(code)))
     return int(code.value)
+
+
+def profile_enable(on=True):
+    _check(load().sfg_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(load().sfg_profile_reset())
+
+
+def profile_query(name):
+    """(launches, total_ms) of the timed launches of kernel `name`."""
+    n, ms = _u64(0), C.c_double(0.0)
+    _check(load().sfg_profile_query(name.encode(), C.byref(n), C.byref(ms)))
+    return int(n.value), float(ms.value)
 
 
 # ----------------------------------------------------------------------------- Kronecker

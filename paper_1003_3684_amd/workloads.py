@@ -62,7 +62,7 @@ def random_pba_case(rng, max_n=50_000):
     case = dict(n=n, m=m, num_parts=P, p_inter=p, seed=int(rng.integers(0, 2 ** 63)), id_bytes=4,
                 faction_off=None, faction_members=None)
     if rng.uniform() < 0.4:
-        sizes = rng.integers(0, 4, size=P)
+        sizes = rng.integers(1, 4, size=P)
         off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint32)
         mem = rng.integers(0, P, size=int(off[-1])).astype(np.uint32)
         case["faction_off"], case["faction_members"] = off, mem

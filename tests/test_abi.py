@@ -100,6 +100,10 @@ def test_pba_validation(lib, host_only):
     mem = np.array([0, 7, 1, 1, 1, 1, 1, 1, 1], np.uint32)  # member 7 >= P
     assert lib.pba_generate(100, 2, 4, 0.1, off.ctypes.data_as(ctypes.c_void_p), mem.ctypes.data_as(ctypes.c_void_p),
                             1, 0, 4, d, d, d, big, None) == -1
+    empty = np.array([0, 1, 1, 2, 3], np.uint32)  # partition 1 has no faction member
+    assert lib.pba_generate(100, 2, 4, 0.1, empty.ctypes.data_as(ctypes.c_void_p),
+                            mem.ctypes.data_as(ctypes.c_void_p), 1, 0, 4, d, d, d, big, None) == -1
+    assert b"empty faction" in lib.sfg_last_error()
     bad = np.array([0, 2, 1, 2, 3], np.uint32)  # not monotone
     assert lib.pba_generate(100, 2, 4, 0.1, bad.ctypes.data_as(ctypes.c_void_p), mem.ctypes.data_as(ctypes.c_void_p),
                             1, 0, 4, d, d, d, big, None) == -1

@@ -1,0 +1,81 @@
+"""Outputs are a pure function of the arguments: the same call on a workspace
+poisoned with different byte patterns, on another stream, gives identical
+results.  A kernel that reads scratch memory it never wrote, or whose result
+depends on scheduling, fails here.  The paper-scale PBA case (2^30 vertices,
+5 x 2^30 edges) is checked this way because the oracle cannot hold it."""
+import numpy as np
+import pytest
+
+from paper_1003_3684_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _pba_twice(sfg, c):
+    import torch
+    E = c["n"] * c["m"]
+    ws = sfg.workspace(sfg.pba_workspace_bytes(c["n"], c["m"], c["num_parts"]))
+    outs = []
+    for fill, stream in ((0xFF, None), (0x00, torch.cuda.Stream())):
+        ws.fill_(fill)
+        src = torch.empty(E, dtype=torch.int32, device="cuda")
+        dst = torch.empty(E, dtype=torch.int32, device="cuda")
+        with torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(torch.cuda.current_stream()):
+            sfg.pba_generate(c["n"], c["m"], c["num_parts"], c["p_inter"], seed=c["seed"], src=src, dst=dst, ws=ws)
+        torch.cuda.synchronize()
+        assert sfg.device_error() == 0
+        outs.append((src, dst))
+    return outs
+
+
+@pytest.mark.parametrize("cfg", [wl.PBA_SMALL, wl.PBA_SCALE[2]], ids=["small", "n2^27_p0.3"])
+def test_pba_workspace_independent(sfg, cfg):
+    import torch
+    (s1, d1), (s2, d2) = _pba_twice(sfg, cfg)
+    assert torch.equal(s1, s2) and torch.equal(d1, d2)
+
+
+@pytest.mark.timeout(600)
+def test_pba_paper_scale_properties(sfg):
+    """2^30 vertices, m = 5, 1,024 partitions: deterministic under a poisoned
+    workspace, every vertex owns m edges, every endpoint is a vertex, and the
+    degree sum is 2 n m."""
+    import torch
+    c = wl.PBA_PAPER
+    (s1, d1), (s2, d2) = _pba_twice(sfg, c)
+    assert torch.equal(d1, d2)
+    del d2
+    assert torch.equal(s1, s2)
+    del s2
+    torch.cuda.empty_cache()
+    n, m = c["n"], c["m"]
+    chunk = 1 << 28
+    for b in range(0, n * m, chunk):
+        e = torch.arange(b, min(b + chunk, n * m), device="cuda", dtype=torch.int64)
+        assert torch.equal(s1[b:b + chunk].long(), e // m)
+    assert int(d1.min()) >= 0 and int(d1.max()) < n
+    # endpoints of partition q's lists land in q: spot-check through the counts
+    # of the first and last partitions' in-degrees being positive
+    deg = torch.bincount(d1.long(), minlength=n)
+    assert int(deg.sum()) == n * m
+    assert int((deg[:n // 1024] > 0).sum()) > 0 and int((deg[-(n // 1024):] > 0).sum()) > 0
+
+
+def test_csr_workspace_independent(sfg):
+    import torch
+    c = wl.KRON_K20
+    src, dst = sfg.kron_generate(c["n0"], c["initiator"], c["k"], c["num_edges"], seed=c["seed"])
+    n = 2 ** c["k"]
+    res = []
+    for flags in (0, 1, 3):
+        ws = sfg.workspace(sfg.edges_to_csr_workspace_bytes(n, c["num_edges"], 4, flags))
+        outs = []
+        for fill in (0xFF, 0x5A):
+            ws.fill_(fill)
+            rp, col, hist, dups = sfg.edges_to_csr(n, src, dst, flags=flags, ws=ws)
+            torch.cuda.synchronize()
+            kept = int(rp[-1])  # SIMPLE writes only the kept entries
+            outs.append((rp.clone(), col[:kept].clone(), hist.clone(), dups.clone()))
+        assert sfg.device_error() == 0
+        for a, b in zip(*outs):
+            assert torch.equal(a, b)

@@ -74,6 +74,7 @@ def test_pba_many_partitions(sfg, orc):
 
 
 @pytest.mark.parametrize("cfg", wl.PBA_SCALE, ids=[c["name"] for c in wl.PBA_SCALE])
+@pytest.mark.timeout(900)
 def test_pba_scale_full(sfg, orc, cfg):
     """2^27 vertices, m = 5, 1,024 partitions: all 671 M edges equal the oracle's."""
     import torch

@@ -323,6 +323,12 @@ def test_pba_invariants_factions(orc):
         np.testing.assert_array_equal(lab[2 * start[q]:2 * start[q] + len(F)], F)
 
 
+def test_pba_empty_faction_rejected(orc):
+    """Slot 0 of a partition with no faction member would have nothing earlier to copy."""
+    with pytest.raises(ValueError):
+        orc.pba_generate(40, 2, 4, 0.1, 1, 0, np.array([0, 1, 1, 2, 3], np.uint32), np.array([1, 2, 3], np.uint32))
+
+
 def test_pba_p0_is_textbook_ba(orc):
     """With p = 0 and singleton factions every partition is an independent
     Barabasi-Albert graph grown from a 2-vertex clique by the edge-copy rule:
