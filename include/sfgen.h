@@ -188,6 +188,113 @@ int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *ds
                  uint64_t *row_ptr, void *col, uint64_t *degree_hist32, uint64_t *num_duplicates,
                  void *workspace, size_t workspace_bytes, void *stream);
 
+/* ------------------------------------------------------------------------
+ * graph_stats -- statistics of one edge list, as the paper characterises its
+ * graphs (Results: degree distributions with fitted exponents, Fig. 3).
+ *
+ * degree_hist32: device [32] uint64, the histogram of edges_to_csr of
+ *                deg(v) = out + in degree (a self-loop adds 2).
+ * gamma:         device [1] double: the discrete power-law maximum-likelihood
+ *                estimate of Clauset, Shalizi & Newman (2009),
+ *                1 + N_t / sum_{d >= d_min} ln(d / (d_min - 1/2)) with
+ *                d_min = 2 ceil(2E / n); NaN when no vertex reaches d_min.
+ *                Summed in a fixed order: identical on every run and device.
+ * closed:        device [1] int64: among num_samples wedges of the simple
+ *                undirected graph (symmetrized, self-loops and repeats
+ *                removed) -- centre v drawn with probability proportional to
+ *                C(deg v, 2) from Philox block (i, 0, 0, tag 4), two distinct
+ *                neighbours uniform -- the number whose ends are adjacent;
+ *                -1 if the graph has no wedge.
+ * workspace:     device, graph_stats_workspace_bytes(n, num_edges, id_bytes).
+ * Errors: as edges_to_csr, plus EINVAL for NULL outputs or graph_id >= 2^24.
+ * ---------------------------------------------------------------------- */
+size_t graph_stats_workspace_bytes(uint64_t n, uint64_t num_edges, int id_bytes);
+int graph_stats(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes, uint32_t num_samples,
+                uint64_t seed, uint32_t graph_id, uint64_t *degree_hist32, double *gamma, int64_t *closed,
+                void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * ensemble_generate -- a batched ensemble of graphs (PBA and Kronecker
+ * members of uneven size and parameters), each summarised by graph_stats.
+ *
+ * Member i equals the single-graph call with the same parameters and graph
+ * id: pba_generate(n, m, num_parts, p_inter, NULL, NULL, seed, graph_id, ...)
+ * or kron_generate(n0, initiator, k, num_edges, SFG_KRON_SAMPLE, seed,
+ * graph_id, ...), followed by graph_stats(..., num_samples, stat_seed,
+ * graph_id, ...).  Its outputs go to degree_hist32[32 i .. 32 i + 31],
+ * gamma[i] and closed[i] (device arrays of count entries), bit for bit the
+ * single-graph results.
+ *
+ * Members are processed in batches cut greedily, in descriptor order, at
+ * max_batch_edges edges: a batch shares one vertex space and edge list, goes
+ * through each generation, sort and statistics kernel once, and reuses the
+ * workspace.  descs is a host array (read before the call returns; the call
+ * waits for its small table uploads).  Kronecker members need n0 <= 4 and
+ * n0^k <= 2^32; PBA members use the default factions.
+ * workspace: device, ensemble_workspace_bytes(descs, count, max_batch_edges).
+ * Errors: EINVAL / ERANGE as the single-graph calls, ENOSPACE.
+ * ---------------------------------------------------------------------- */
+enum { SFG_GRAPH_PBA = 0, SFG_GRAPH_KRON = 1 };
+
+typedef struct {
+    int32_t kind;         /* SFG_GRAPH_PBA or SFG_GRAPH_KRON          */
+    uint32_t graph_id;    /* < 2^24                                    */
+    uint64_t seed;        /* Philox key of the member's generation     */
+    uint64_t n;           /* PBA: vertices                             */
+    uint32_t m;           /* PBA: edges per vertex                     */
+    uint32_t num_parts;   /* PBA: partitions                           */
+    double p_inter;       /* PBA: inter-faction probability            */
+    uint32_t n0;          /* Kronecker: initiator side (2..4)          */
+    uint32_t k;           /* Kronecker: levels                         */
+    uint64_t num_edges;   /* Kronecker: sampled edges                  */
+    float initiator[16];  /* Kronecker: n0*n0 weights, row-major       */
+} sfg_graph_desc;
+
+size_t ensemble_workspace_bytes(const sfg_graph_desc *descs, uint32_t count, uint64_t max_batch_edges);
+int ensemble_generate(const sfg_graph_desc *descs, uint32_t count, uint32_t num_samples, uint64_t stat_seed,
+                      uint64_t max_batch_edges, uint64_t *degree_hist32, double *gamma, int64_t *closed,
+                      void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * MLP surrogate -- maps generator parameters to graph statistics; trained on
+ * ensembles of generated graphs and inverted to choose parameters for a
+ * target degree exponent (the generator stays the judge of the result).
+ *
+ * Shape: d_in -> width -> ... -> width -> d_out with `hidden` SiLU layers
+ * and a linear output layer.  params: device float32, for each layer W
+ * (out x in, row-major) then b (out); mlp_param_count gives its length.
+ * Every GEMM reads bfloat16 weights and inputs (round to nearest even) and
+ * accumulates in float32 on the matrix cores; biases, activations and
+ * gradients are float32.  Rounding points: Xb_0 = bf16(x); Z = Xb Wb^T + b;
+ * next Xb = bf16(SiLU(Z)); backward dZb = bf16(dZ), dW = dZb^T Xb,
+ * db = column sums of dZ, dH = dZb Wb.
+ * workspace: device, mlp_workspace_bytes(shape, batch); mlp_forward leaves
+ * the activations there for the following mlp_backward on the same batch.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    uint32_t d_in, width, d_out, hidden;
+} sfg_mlp_shape;
+
+size_t mlp_param_count(const sfg_mlp_shape *shape);
+size_t mlp_workspace_bytes(const sfg_mlp_shape *shape, uint32_t batch);
+/* y: device [batch][d_out] from x: device [batch][d_in]. */
+int mlp_forward(const sfg_mlp_shape *shape, uint32_t batch, const float *params, const float *x, float *y,
+                void *workspace, size_t workspace_bytes, void *stream);
+/* grad (device, param count; nullable) and dx (device [batch][d_in]; nullable,
+ * the gradient with respect to x, passed straight through the input rounding)
+ * from dy = dLoss/dy. */
+int mlp_backward(const sfg_mlp_shape *shape, uint32_t batch, const float *params, const float *dy, float *grad,
+                 float *dx, void *workspace, size_t workspace_bytes, void *stream);
+/* loss = sum_{b,j} w_j mask_bj (y_bj - t_bj)^2 / batch and dy = dloss/dy;
+ * mask [batch][d_out] and col_weight [d_out] are nullable (ones); loss is a
+ * device float; workspace holds batch floats. */
+int mlp_mse_grad(uint32_t batch, uint32_t d_out, const float *y, const float *target, const float *mask,
+                 const float *col_weight, float *dy, float *loss, void *workspace, size_t workspace_bytes,
+                 void *stream);
+/* Adam (Kingma & Ba) with bias correction; step counts from 1. */
+int adam_step(uint64_t count, float *params, const float *grad, float *m, float *v, float lr, float beta1, float beta2,
+              float eps, uint32_t step, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

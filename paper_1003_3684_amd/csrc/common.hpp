@@ -26,6 +26,15 @@ struct ProfScope {
     const char *kname;
 };
 
+// CSR construction shared by edges_to_csr and the statistics entry points.
+// raw_rows (optional) receives the device address of the row starts of the
+// uncompacted entry list (n+1 values; inside the workspace when SIMPLE and a
+// histogram are requested, else row_ptr itself).
+size_t csr_workspace_bytes(uint64_t n, uint64_t num_edges, int id_bytes, uint32_t flags);
+int csr_build(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes, uint32_t flags,
+              uint64_t *row_ptr, void *col, uint64_t *degree_hist32, uint64_t *num_duplicates, void *workspace,
+              size_t workspace_bytes, hipStream_t s, const uint64_t **raw_rows);
+
 // Counter-word tags of the Philox streams.
 enum : uint32_t { TAG_KRON = 1, TAG_PBA1 = 2, TAG_PBA2 = 3, TAG_WEDGE = 4 };
 

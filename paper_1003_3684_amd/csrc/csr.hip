@@ -31,10 +31,11 @@ namespace sfg {
 namespace {
 
 constexpr int kPassThreads = 512;
-constexpr int kPassItems = 16;
+constexpr int kPassItems = 8;
 constexpr int kPassTile = kPassThreads * kPassItems;  // keys per onesweep tile
 constexpr int kPassWaves = kPassThreads / 64;
 constexpr int kRadix = 256;
+constexpr int kLookWindow = 4;  // predecessors read per look-back round trip
 
 constexpr int kFinThreads = 256;
 constexpr int kFinItems = 16;
@@ -151,39 +152,50 @@ struct PassArgs {
 // of every destination run in csc.
 template <typename IdT, typename KeyT, bool SYM, bool FIRST, bool BOUND>
 __global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
+    // s_keys holds the tile's keys in digit order after ranking; during the
+    // ranking its first 16 KB serve as the per-wave lane-match tables.
     __shared__ KeyT s_keys[kPassTile];
-    __shared__ uint32_t s_cnt[kPassWaves][kRadix];
-    __shared__ uint32_t s_off[kRadix];
+    // 16-bit counters keep the block at about 38 KB of LDS: four tiles per CU.
+    __shared__ uint16_t s_cnt[kPassWaves][kRadix];
+    __shared__ uint16_t s_off[kRadix];
     __shared__ uint64_t s_gpos[kRadix];
     __shared__ uint64_t s_tmp[4];
     __shared__ uint32_t s_tile;
+    static_assert(sizeof(KeyT) * kPassTile >= sizeof(uint64_t) * kPassWaves * kRadix, "match tables do not fit");
+    uint64_t *s_match = reinterpret_cast<uint64_t *>(s_keys) + 0;  // [kPassWaves][256]
 
     const int tid = threadIdx.x;
     const uint32_t lane = tid & 63;
     const int w = tid >> 6;
-    if (tid == 0) s_tile = fetch_add_agent(a.ticket, 1u);
-    for (int i = tid; i < kPassWaves * kRadix; i += kPassThreads) (&s_cnt[0][0])[i] = 0;
+    // Tile = workgroup id.  Workgroups are dispatched in id order (round-robin
+    // over the XCDs), so every tile this one waits for in the look-back was
+    // dispatched earlier and is running or done: the smallest unfinished tile
+    // never waits.  A single ticket counter would serialise the tiles on one
+    // device-coherent atomic.
+    if (tid == 0) s_tile = blockIdx.x;
+    for (int i = tid; i < kPassWaves * kRadix; i += kPassThreads) {
+        (&s_cnt[0][0])[i] = 0;
+        s_match[i] = 0;
+    }
     __syncthreads();
     const uint64_t tile = s_tile;
     const uint64_t tile_base = tile * kPassTile;
     const uint64_t wbase = tile_base + (uint64_t)w * 64 * kPassItems;
+    const bool full = tile_base + kPassTile <= a.N;
 
     KeyT k[kPassItems];
     uint32_t d[kPassItems];
 #pragma unroll
     for (int i = 0; i < kPassItems; ++i) {
         const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
-        if (idx < a.N) {
-            if (FIRST)
-                k[i] = entry_key<IdT, KeyT, SYM>(static_cast<const IdT *>(a.src), static_cast<const IdT *>(a.dst), a.E,
-                                                  idx, a.wb);
-            else
-                k[i] = static_cast<const KeyT *>(a.in)[idx];
-            d[i] = (uint32_t)(k[i] >> a.shift) & 255u;
-        } else {
-            k[i] = 0;
-            d[i] = kRadix;  // no digit
-        }
+        const bool valid = full || idx < a.N;
+        if (FIRST)
+            k[i] = valid ? entry_key<IdT, KeyT, SYM>(static_cast<const IdT *>(a.src), static_cast<const IdT *>(a.dst),
+                                                      a.E, idx, a.wb)
+                         : (KeyT)0;
+        else
+            k[i] = valid ? static_cast<const KeyT *>(a.in)[idx] : (KeyT)0;
+        d[i] = valid ? (uint32_t)(k[i] >> a.shift) & 255u : (uint32_t)kRadix;
     }
 
     if (BOUND) {
@@ -202,24 +214,31 @@ __global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
         }
     }
 
-    // Stable rank inside the wave: lanes with equal digits are found with 8
-    // ballots; the lowest lane of each group advances the wave's counter.
+    // Stable rank inside the wave.  For each group of 64 keys every lane ORs
+    // its lane bit into the wave's match slot of its digit; reading the slot
+    // back gives the lanes sharing the digit (OR is order-free, so the mask
+    // is exact).  Lanes below this one in the mask come first; the lowest
+    // lane of each digit advances the wave's counter and clears the slot.
+    // LDS operations of one wave complete in program order.
     uint32_t r[kPassItems];
+    uint64_t *match = s_match + w * kRadix;
+    uint16_t *wcnt = s_cnt[w];
+    const uint64_t my_bit = 1ull << lane;
 #pragma unroll
     for (int i = 0; i < kPassItems; ++i) {
         const uint32_t di = d[i];
-        uint64_t peers = __ballot(di < kRadix);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (di >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
-        }
-        if (di < kRadix) {
-            const uint32_t below = count_below(peers);
-            const uint32_t old = s_cnt[w][di];
-            r[i] = old + below;
-            if (below == 0) s_cnt[w][di] = old + (uint32_t)__popcll(peers);
+        const bool valid = di < kRadix;
+        const uint32_t slot = valid ? di : 0;
+        if (valid) atomicOr(reinterpret_cast<unsigned long long *>(&match[slot]), (unsigned long long)my_bit);
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t peers = valid ? match[slot] : 0ull;
+        const uint32_t below = count_below(peers);
+        const uint32_t old = wcnt[slot];
+        r[i] = old + below;
+        __builtin_amdgcn_wave_barrier();
+        if (valid && below == 0) {
+            wcnt[slot] = (uint16_t)(old + (uint32_t)__popcll(peers));
+            match[slot] = 0;
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -232,7 +251,7 @@ __global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
 #pragma unroll
         for (int wv = 0; wv < kPassWaves; ++wv) {
             const uint32_t c = s_cnt[wv][tid];
-            s_cnt[wv][tid] = acc;
+            s_cnt[wv][tid] = (uint16_t)acc;
             acc += c;
         }
         cnt = acc;
@@ -242,29 +261,43 @@ __global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
 
     // Decoupled look-back: the number of keys with digit d in earlier tiles.
     if (tid < kRadix) {
-        s_off[tid] = (uint32_t)ex;
+        s_off[tid] = (uint16_t)ex;
         uint64_t *st = a.status + tile * kRadix + tid;
         uint64_t prefix = 0;
         if (tile == 0) {
             store_agent(st, status_word(a.tag, kFlagIncl, cnt));
         } else {
             store_agent(st, status_word(a.tag, kFlagAgg, cnt));
-            uint64_t j = tile - 1;
-            for (;;) {
-                const uint64_t *pj = a.status + j * kRadix + tid;
-                uint64_t v = load_agent(pj);
-                uint32_t spins = 0;
-                while ((uint32_t)(v >> 58) != a.tag) {
-                    if (++spins > kSpinLimit || ((spins & 1023) == 0 && load_agent(a.err) != 0)) {
-                        raise_device_error(a.err, DEVERR_LOOKBACK);
-                        break;
+            // Look back over kLookWindow predecessors per round trip: read
+            // them together, then add counts from the nearest one back until
+            // an inclusive prefix; a predecessor not yet published is
+            // re-read until it is.
+            uint64_t j = tile;  // tiles below j are still to be examined
+            bool done = false;
+            while (!done) {
+                uint64_t v[kLookWindow];
+#pragma unroll
+                for (int i = 0; i < kLookWindow; ++i)
+                    v[i] = (j > (uint64_t)i) ? load_agent(a.status + (j - 1 - i) * kRadix + tid) : 0;
+#pragma unroll
+                for (int i = 0; i < kLookWindow; ++i) {
+                    if (done || j <= (uint64_t)i) break;
+                    const uint64_t *pj = a.status + (j - 1 - i) * kRadix + tid;
+                    uint32_t spins = 0;
+                    while ((uint32_t)(v[i] >> 58) != a.tag) {
+                        if (++spins > kSpinLimit || ((spins & 1023) == 0 && load_agent(a.err) != 0)) {
+                            raise_device_error(a.err, DEVERR_LOOKBACK);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                        v[i] = load_agent(pj);
                     }
-                    __builtin_amdgcn_s_sleep(1);
-                    v = load_agent(pj);
+                    prefix += v[i] & ((1ull << 56) - 1);
+                    if (((v[i] >> 56) & 3) == kFlagIncl || (uint32_t)(v[i] >> 58) != a.tag || j - 1 - i == 0)
+                        done = true;
                 }
-                prefix += v & ((1ull << 56) - 1);
-                if (((v >> 56) & 3) == kFlagIncl || (uint32_t)(v >> 58) != a.tag || j == 0) break;
-                --j;
+                j = j > (uint64_t)kLookWindow ? j - kLookWindow : 0;
+                if (j == 0) done = true;
             }
             store_agent(st, status_word(a.tag, kFlagIncl, prefix + cnt));
         }
@@ -301,15 +334,64 @@ struct FinArgs {
     int wb;
 };
 
+__device__ __forceinline__ int fin_slot(int i) { return i + (i >> 4); }
+
+// Non-SIMPLE finish: one streaming pass with no LDS.  Thread t of a block
+// owns positions base + j*256 + t; the key before position idx comes from the
+// previous lane (or, for lane 0, from memory).
+template <typename IdT, typename KeyT>
+__global__ __launch_bounds__(kFinThreads) void csr_finish_plain(FinArgs a) {
+    __shared__ uint32_t s_dups[kFinThreads / 64];
+    const int tid = threadIdx.x;
+    const uint32_t lane = tid & 63;
+    const KeyT *K = static_cast<const KeyT *>(a.keys);
+    IdT *col = static_cast<IdT *>(a.col);
+    const KeyT mask = ((KeyT)1 << a.wb) - 1;
+    uint32_t ndup = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * kFinThreads;
+    for (uint64_t idx = (uint64_t)blockIdx.x * kFinThreads + tid; idx - lane < a.N; idx += stride) {
+        const bool valid = idx < a.N;
+        const KeyT key = valid ? K[idx] : (KeyT)0;
+        KeyT prev = __shfl_up(key, 1, 64);
+        if (lane == 0 && idx > 0 && valid) prev = K[idx - 1];
+        if (valid) {
+            col[idx] = (IdT)(key & mask);
+            const uint64_t row = (uint64_t)(key >> a.wb);
+            if (idx == 0 || row != (uint64_t)(prev >> a.wb)) {
+                a.rp[row] = idx;
+                if (a.rp_raw) a.rp_raw[row] = idx;
+            }
+            ndup += (idx > 0 && key == prev) ? 1u : 0u;
+            if (idx == a.N - 1) {
+                a.rp[a.n] = a.N;
+                if (a.rp_raw) a.rp_raw[a.n] = a.N;
+            }
+        }
+    }
+    if (a.dups) {
+        uint32_t x = ndup;
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+        if (lane == 0) s_dups[tid >> 6] = x;
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t t = 0;
+            for (int i = 0; i < kFinThreads / 64; ++i) t += s_dups[i];
+            if (t) atomicAdd((unsigned long long *)a.dups, (unsigned long long)t);
+        }
+    }
+}
+
 template <typename IdT, typename KeyT, bool SIMPLE>
 __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
-    __shared__ KeyT s_keys[kFinTile + 1];
+    // Blocked reads (16 consecutive keys per thread) would hit one LDS bank
+    // for the whole wave; one pad slot per 16 keys spreads them.
+    __shared__ KeyT s_keys[kFinTile + kFinTile / 16 + 2];
     __shared__ uint64_t s_tmp[4];
     __shared__ uint64_t s_base;
     __shared__ uint32_t s_tile;
     __shared__ uint32_t s_dups[kFinThreads / 64];
     const int tid = threadIdx.x;
-    if (tid == 0) s_tile = SIMPLE ? fetch_add_agent(a.ticket, 1u) : blockIdx.x;
+    if (tid == 0) s_tile = blockIdx.x;  // dispatch order (see radix_pass)
     __syncthreads();
     const uint64_t tile = s_tile;
     const uint64_t t0 = tile * kFinTile;
@@ -317,7 +399,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
     // Striped (coalesced) load into LDS; slot 0 holds the key before the tile.
     for (int i = tid; i < kFinTile; i += kFinThreads) {
         const uint64_t idx = t0 + i;
-        s_keys[i + 1] = idx < a.N ? K[idx] : (KeyT)0;
+        s_keys[fin_slot(i + 1)] = idx < a.N ? K[idx] : (KeyT)0;
     }
     if (tid == 0) s_keys[0] = t0 > 0 ? K[t0 - 1] : (KeyT)0;
     __syncthreads();
@@ -329,7 +411,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
         const int p = tid * kFinItems + j;
         const uint64_t idx = t0 + p;
         if (idx < a.N) {
-            const KeyT key = s_keys[p + 1], prev = s_keys[p];
+            const KeyT key = s_keys[fin_slot(p + 1)], prev = s_keys[fin_slot(p)];
             const bool dup = idx > 0 && key == prev;
             ndup += dup;
             const bool keep = !SIMPLE || (!dup && (key >> a.wb) != (key & mask));
@@ -381,7 +463,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
         const int p = tid * kFinItems + j;
         const uint64_t idx = t0 + p;
         if (idx < a.N) {
-            const KeyT key = s_keys[p + 1], prev = s_keys[p];
+            const KeyT key = s_keys[fin_slot(p + 1)], prev = s_keys[fin_slot(p)];
             const uint64_t row = (uint64_t)(key >> a.wb);
             if (idx == 0 || row != (uint64_t)(prev >> a.wb)) {
                 a.rp[row] = c;
@@ -398,7 +480,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
         // Columns, striped for coalesced stores.
         for (int i = tid; i < kFinTile; i += kFinThreads) {
             const uint64_t idx = t0 + i;
-            if (idx < a.N) col[idx] = (IdT)(s_keys[i + 1] & mask);
+            if (idx < a.N) col[idx] = (IdT)(s_keys[fin_slot(i + 1)] & mask);
         }
     }
     if (a.dups) {
@@ -660,7 +742,7 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
         if (P.simple)
             { ProfScope _ps("csr_finish", s); csr_finish<IdT, KeyT, true><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa); }
         else
-            { ProfScope _ps("csr_finish", s); csr_finish<IdT, KeyT, false><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa); }
+            { ProfScope _ps("csr_finish", s); csr_finish_plain<IdT, KeyT><<<fill_grid(P.N), kFinThreads, 0, s>>>(fa); }
     } else {
         fill<uint64_t>(row_ptr + P.n, 1, 0, s);
         if (rp_raw_ws) fill<uint64_t>(rp_raw_ws + P.n, 1, 0, s);
@@ -684,13 +766,19 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
 using namespace sfg;
 
 extern "C" size_t edges_to_csr_workspace_bytes(uint64_t n, uint64_t num_edges, int id_bytes, uint32_t flags) {
+    return sfg::csr_workspace_bytes(n, num_edges, id_bytes, flags);
+}
+
+namespace sfg {
+
+size_t csr_workspace_bytes(uint64_t n, uint64_t num_edges, int id_bytes, uint32_t flags) {
     if (n == 0) return 0;
     return make_plan(n, num_edges, id_bytes, flags, true).total;
 }
 
-extern "C" int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes,
-                            uint32_t flags, uint64_t *row_ptr, void *col, uint64_t *degree_hist32,
-                            uint64_t *num_duplicates, void *workspace, size_t workspace_bytes, void *stream) {
+int csr_build(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes, uint32_t flags,
+              uint64_t *row_ptr, void *col, uint64_t *degree_hist32, uint64_t *num_duplicates, void *workspace,
+              size_t workspace_bytes, hipStream_t s, const uint64_t **raw_rows) {
     if (n == 0) return fail(SFG_EINVAL, "edges_to_csr: n must be >= 1");
     if (id_bytes != 4 && id_bytes != 8) return fail(SFG_EINVAL, "edges_to_csr: id_bytes must be 4 or 8");
     if (flags & ~(uint32_t)(SFG_CSR_SYMMETRIZE | SFG_CSR_SIMPLE)) return fail(SFG_EINVAL, "edges_to_csr: bad flags");
@@ -708,12 +796,21 @@ extern "C" int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, con
     if (workspace_bytes < P.total)
         return fail(SFG_ENOSPACE, "edges_to_csr: workspace has %zu bytes, needs %zu", workspace_bytes, P.total);
     if (!device_error_word()) return fail(SFG_EDEVICE, "edges_to_csr: no device");
-    hipStream_t s = as_stream(stream);
     char *ws = static_cast<char *>(workspace);
+    if (raw_rows) *raw_rows = (P.hist && P.simple) ? reinterpret_cast<const uint64_t *>(ws + P.off_rpraw) : row_ptr;
     if (P.key_bytes == 4) {
         if (id_bytes == 4) return run_csr<int32_t, uint32_t>(P, src, dst, row_ptr, col, degree_hist32, num_duplicates, ws, s);
         return run_csr<int64_t, uint32_t>(P, src, dst, row_ptr, col, degree_hist32, num_duplicates, ws, s);
     }
     if (id_bytes == 4) return run_csr<int32_t, uint64_t>(P, src, dst, row_ptr, col, degree_hist32, num_duplicates, ws, s);
     return run_csr<int64_t, uint64_t>(P, src, dst, row_ptr, col, degree_hist32, num_duplicates, ws, s);
+}
+
+}  // namespace sfg
+
+extern "C" int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes,
+                            uint32_t flags, uint64_t *row_ptr, void *col, uint64_t *degree_hist32,
+                            uint64_t *num_duplicates, void *workspace, size_t workspace_bytes, void *stream) {
+    return csr_build(n, num_edges, src, dst, id_bytes, flags, row_ptr, col, degree_hist32, num_duplicates, workspace,
+                     workspace_bytes, as_stream(stream), nullptr);
 }

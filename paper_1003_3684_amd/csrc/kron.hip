@@ -20,20 +20,14 @@
 #include <vector>
 
 #include "common.hpp"
+#include "kron.hpp"
 
 namespace sfg {
 namespace {
 
 constexpr int kBlock = 256;
 
-// Thresholds of the sample mode in the form the kernels use.  With the
-// distinct cumulative thresholds v_1 < v_2 < ... (those below 2^32, v_i >= 1),
-// a word w selects bucket b = #{i : w > v_i - 1}; the cell is lut[b].
-struct SampleTable {
-    uint32_t nt = 0;             // number of distinct thresholds >= 1
-    uint32_t tm1[255];           // v_i - 1, ascending
-    uint8_t row[256], col[256];  // cell digits of bucket b
-};
+}  // namespace
 
 int build_sample_table(uint32_t n0, const float *W, SampleTable &tab) {
     const uint32_t C = n0 * n0;
@@ -78,6 +72,8 @@ int build_sample_table(uint32_t n0, const float *W, SampleTable &tab) {
     }
     return SFG_OK;
 }
+
+namespace {
 
 // Kernel arguments of the register path (at most 15 distinct thresholds and
 // digits below 16): thresholds live in scalar registers, the bucket-to-digit

@@ -1,0 +1,395 @@
+// MLP surrogate of the generators: parameters -> graph statistics.
+//
+// d_in -> width -> ... -> width -> d_out, `hidden` SiLU layers, the output
+// layer linear.  Master parameters are float32; every GEMM reads its weights
+// and its input activations rounded to bfloat16 (round to nearest even) and
+// accumulates in float32 on the matrix cores (v_mfma_f32_16x16x32_bf16).
+// Biases, pre-activations, activations and every gradient stay float32.
+// Rounding points:
+//   forward   Xb_0 = bf16(x); Z_l = Xb_l Wb_l^T + b_l; Xb_{l+1} = bf16(SiLU(Z_l))
+//   backward  dZb_l = bf16(dZ_l); dW_l = dZb_l^T Xb_l; db_l = sum_b dZ_l;
+//             dH_{l-1} = dZb_l Wb_l; dZ_{l-1} = dH_{l-1} * SiLU'(Z_{l-1})
+// with Wb_l = bf16(W_l).  Parameter layout: for each layer, W (out x in,
+// row-major) then b (out).
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+
+namespace sfg {
+namespace {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+
+constexpr int kTile = 64;   // block tile (M and N)
+constexpr int kKStep = 32;  // K per MFMA step
+constexpr int kPad = 8;     // LDS row padding (bf16 elements)
+
+// float -> bfloat16, round to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint16_t f2bf_bits(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ bf16 f2bf(float f) {
+    const uint16_t b = f2bf_bits(f);
+    return __builtin_bit_cast(bf16, b);
+}
+__device__ __forceinline__ float bf2f(bf16 h) {
+    const uint16_t b = __builtin_bit_cast(uint16_t, h);
+    return __uint_as_float((uint32_t)b << 16);
+}
+
+// C[M][N] (+)= sum_k A(m, k) B(k, n) over k in [k_begin, k_end), with
+// A(m, k) = TA ? A[k * lda + m] : A[m * lda + k] and
+// B(k, n) = TB ? B[n * ldb + k] : B[k * ldb + n]; bf16 in, fp32 out.
+// Block: 256 threads, a 64 x 64 tile; wave w owns rows 32 (w / 2) .. +32 and
+// columns 32 (w % 2) .. +32 as 2 x 2 MFMA 16 x 16 tiles.  Split-K: blockIdx.z
+// selects a K range and a partial output C + z * M * N.
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void gemm_bf16(const bf16 *__restrict__ A, int lda, const bf16 *__restrict__ B,
+                                                 int ldb, float *__restrict__ C, int M, int N, int K, int ksplit) {
+    __shared__ bf16 sA[kTile][kKStep + kPad];  // [m][k]
+    __shared__ bf16 sB[kTile][kKStep + kPad];  // [n][k]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
+    const int kper = ((K + ksplit - 1) / ksplit + kKStep - 1) / kKStep * kKStep;
+    const int kb = blockIdx.z * kper, ke = std::min(K, kb + kper);
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bf16 zero = f2bf(0.f);
+    for (int k0 = kb; k0 < ke; k0 += kKStep) {
+        for (int i = tid; i < kTile * kKStep; i += 256) {
+            int m, k;
+            if (TA) {  // consecutive threads along m
+                m = i % kTile;
+                k = i / kTile;
+            } else {
+                k = i % kKStep;
+                m = i / kKStep;
+            }
+            const int gm = m0 + m, gk = k0 + k;
+            sA[m][k] = (gm < M && gk < ke) ? (TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk]) : zero;
+            int n, kk;
+            if (TB) {
+                kk = i % kKStep;
+                n = i / kKStep;
+            } else {
+                n = i % kTile;
+                kk = i / kTile;
+            }
+            const int gn = n0 + n, gk2 = k0 + kk;
+            sB[n][kk] = (gn < N && gk2 < ke) ? (TB ? B[(size_t)gn * ldb + gk2] : B[(size_t)gk2 * ldb + gn]) : zero;
+        }
+        __syncthreads();
+        // 16x16x32 operands: lane l holds row/col (l % 16), k = 8 (l / 16) .. +7.
+        const int r = lane % 16, kq = 8 * (lane / 16);
+        bf16x8 fa[2], fb[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int mr = 32 * (w / 2) + 16 * i + r;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) fa[i][e] = sA[mr][kq + e];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int nc = 32 * (w % 2) + 16 * j + r;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) fb[j][e] = sB[nc][kq + e];
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // Result: lane l holds rows 4 (l / 16) .. +3 and column l % 16 of each tile.
+    float *Cz = C + (size_t)blockIdx.z * M * N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = m0 + 32 * (w / 2) + 16 * i + 4 * (lane / 16) + e;
+                const int gn = n0 + 32 * (w % 2) + 16 * j + lane % 16;
+                if (gm < M && gn < N) Cz[(size_t)gm * N + gn] = acc[i][j][e];
+            }
+}
+
+__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// bf16 copy of every weight matrix of the parameter vector.
+__global__ void round_weights(const float *p, bf16 *wb, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        wb[i] = f2bf(p[i]);
+}
+
+__global__ void round_input(const float *x, bf16 *xb, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        xb[i] = f2bf(x[i]);
+}
+
+// Z = acc + b (stored), then SiLU -> bf16 next input (hidden) or Y (output).
+__global__ void bias_act(const float *acc, const float *b, float *Z, bf16 *Xnext, float *Y, int rows, int cols) {
+    const uint64_t n = (uint64_t)rows * cols;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const float z = acc[i] + b[i % cols];
+        if (Z) Z[i] = z;
+        if (Xnext) Xnext[i] = f2bf(z * sigmoidf_(z));
+        if (Y) Y[i] = z;
+    }
+}
+
+// dZ = dH * SiLU'(Z) (or dZ = dY for the output layer when Z is null);
+// writes the fp32 dZ and its bf16 copy.
+__global__ void act_grad(const float *dH, const float *Z, float *dZ, bf16 *dZb, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        float g = dH[i];
+        if (Z) {
+            const float z = Z[i], s = sigmoidf_(z);
+            g *= s * (1.0f + z * (1.0f - s));
+        }
+        dZ[i] = g;
+        dZb[i] = f2bf(g);
+    }
+}
+
+// Column sums in a fixed order: db[c] = sum_r dZ[r][c] (one thread per column).
+__global__ void col_sums(const float *dZ, int rows, int cols, float *db) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float acc = 0.f;
+    for (int r = 0; r < rows; ++r) acc += dZ[(size_t)r * cols + c];
+    db[c] = acc;
+}
+
+// out[i] = sum over the split-K partials, in split order.
+__global__ void reduce_splits(const float *part, int splits, uint64_t n, float *out) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        for (int z = 0; z < splits; ++z) acc += part[(uint64_t)z * n + i];
+        out[i] = acc;
+    }
+}
+
+// Weighted squared error: loss = sum_{b,j} w_j mask_bj (y_bj - t_bj)^2 / B,
+// dy = 2 w_j mask_bj (y_bj - t_bj) / B.  Per-row partial losses, then a
+// single-block sum in row order.
+__global__ void mse_grad(const float *y, const float *t, const float *mask, const float *cw, int B, int D, float *dy,
+                         float *row_loss) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float acc = 0.f;
+    for (int j = 0; j < D; ++j) {
+        const size_t i = (size_t)b * D + j;
+        const float wgt = (cw ? cw[j] : 1.f) * (mask ? mask[i] : 1.f);
+        const float d = y[i] - t[i];
+        dy[i] = wgt == 0.f ? 0.f : 2.f * wgt * d / (float)B;
+        acc += wgt == 0.f ? 0.f : wgt * d * d;
+    }
+    row_loss[b] = acc / (float)B;
+}
+
+__global__ void sum_rows(const float *v, int n, float *out) {
+    __shared__ float s[256];
+    float acc = 0.f;
+    for (int i = threadIdx.x; i < n; i += 256) acc += v[i];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = s[0];
+}
+
+__global__ void adam_kernel(uint64_t n, float *p, const float *g, float *m, float *v, float lr, float b1, float b2,
+                            float eps, float c1, float c2) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// ----------------------------------------------------------------------------- host
+struct Layer {
+    int in, out;
+    size_t w_off, b_off;  // in the parameter vector (floats)
+};
+
+struct Net {
+    int L = 0;  // linear layers
+    Layer layer[16];
+    size_t nparams = 0, nweights = 0;
+    int maxw = 0;
+};
+
+bool make_net(const sfg_mlp_shape *s, Net &net) {
+    if (!s || s->d_in == 0 || s->width == 0 || s->d_out == 0 || s->hidden == 0 || s->hidden > 14) return false;
+    if (s->d_in > 4096 || s->width > 4096 || s->d_out > 4096) return false;
+    net.L = (int)s->hidden + 1;
+    size_t off = 0;
+    for (int l = 0; l < net.L; ++l) {
+        const int in = l == 0 ? (int)s->d_in : (int)s->width;
+        const int out = l == net.L - 1 ? (int)s->d_out : (int)s->width;
+        net.layer[l] = Layer{in, out, off, off + (size_t)in * out};
+        off += (size_t)in * out + out;
+        net.maxw = std::max({net.maxw, in, out});
+    }
+    net.nparams = off;
+    return true;
+}
+
+constexpr int kSplits = 8;  // split-K of the weight gradients (reduction over the batch)
+
+struct Ws {
+    bf16 *wb;       // bf16 copy of the whole parameter vector (weights used)
+    bf16 *xb[16];   // layer inputs (bf16)
+    float *z[16];   // pre-activations
+    float *acc;     // GEMM output scratch [B][maxw]
+    float *dz, *dh; // [B][maxw]
+    bf16 *dzb;      // [B][maxw]
+    float *part;    // split-K partials [kSplits][maxw][maxw]
+    float *rowloss; // [B]
+    size_t total;
+};
+
+Ws carve(const Net &net, uint32_t B, void *base) {
+    Ws w;
+    memset(&w, 0, sizeof(w));
+    Carver c(base);
+    w.wb = c.take<bf16>(net.nparams);
+    for (int l = 0; l < net.L; ++l) w.xb[l] = c.take<bf16>((size_t)B * net.layer[l].in);
+    for (int l = 0; l < net.L; ++l) w.z[l] = c.take<float>((size_t)B * net.layer[l].out);
+    w.acc = c.take<float>((size_t)B * net.maxw);
+    w.dz = c.take<float>((size_t)B * net.maxw);
+    w.dh = c.take<float>((size_t)B * net.maxw);
+    w.dzb = c.take<bf16>((size_t)B * net.maxw);
+    w.part = c.take<float>((size_t)kSplits * net.maxw * net.maxw);
+    w.rowloss = c.take<float>(std::max<uint32_t>(B, 1));
+    w.total = c.used;
+    return w;
+}
+
+int grid_n(uint64_t n) { return (int)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 4096)); }
+
+template <bool TA, bool TB>
+void gemm(const bf16 *A, int lda, const bf16 *B, int ldb, float *C, int M, int N, int K, int splits, hipStream_t s) {
+    dim3 g((N + kTile - 1) / kTile, (M + kTile - 1) / kTile, splits);
+    ProfScope _ps("mlp_gemm", s);
+    gemm_bf16<TA, TB><<<g, 256, 0, s>>>(A, lda, B, ldb, C, M, N, K, splits);
+}
+
+}  // namespace
+}  // namespace sfg
+
+using namespace sfg;
+
+extern "C" size_t mlp_param_count(const sfg_mlp_shape *shape) {
+    Net net;
+    return make_net(shape, net) ? net.nparams : 0;
+}
+
+extern "C" size_t mlp_workspace_bytes(const sfg_mlp_shape *shape, uint32_t batch) {
+    Net net;
+    if (!make_net(shape, net)) return 0;
+    return carve(net, batch, nullptr).total;
+}
+
+extern "C" int mlp_forward(const sfg_mlp_shape *shape, uint32_t batch, const float *params, const float *x, float *y,
+                           void *workspace, size_t workspace_bytes, void *stream) {
+    Net net;
+    if (!make_net(shape, net)) return fail(SFG_EINVAL, "mlp_forward: bad shape");
+    if (batch == 0 || batch > (1u << 24)) return fail(SFG_EINVAL, "mlp_forward: batch must be in [1, 2^24]");
+    if (!params || !x || !y || !workspace) return fail(SFG_EINVAL, "mlp_forward: NULL buffer");
+    Ws w = carve(net, batch, workspace);
+    if (workspace_bytes < w.total) return fail(SFG_ENOSPACE, "mlp_forward: workspace too small (%zu < %zu)", workspace_bytes, w.total);
+    hipStream_t s = as_stream(stream);
+    { ProfScope _ps("mlp_elementwise", s); round_weights<<<grid_n(net.nparams), 256, 0, s>>>(params, w.wb, net.nparams); }
+    { ProfScope _ps("mlp_elementwise", s); round_input<<<grid_n((uint64_t)batch * net.layer[0].in), 256, 0, s>>>(x, w.xb[0], (uint64_t)batch * net.layer[0].in); }
+    for (int l = 0; l < net.L; ++l) {
+        const Layer &ly = net.layer[l];
+        // acc[B][out] = Xb[B][in] * Wb[out][in]^T
+        gemm<false, true>(w.xb[l], ly.in, w.wb + ly.w_off, ly.in, w.acc, (int)batch, ly.out, ly.in, 1, s);
+        const bool last = l == net.L - 1;
+        ProfScope _ps("mlp_elementwise", s);
+        bias_act<<<grid_n((uint64_t)batch * ly.out), 256, 0, s>>>(w.acc, params + ly.b_off, w.z[l],
+                                                                   last ? nullptr : w.xb[l + 1], last ? y : nullptr,
+                                                                   (int)batch, ly.out);
+    }
+    return check_launch("mlp_forward");
+}
+
+extern "C" int mlp_backward(const sfg_mlp_shape *shape, uint32_t batch, const float *params, const float *dy,
+                            float *grad, float *dx, void *workspace, size_t workspace_bytes, void *stream) {
+    Net net;
+    if (!make_net(shape, net)) return fail(SFG_EINVAL, "mlp_backward: bad shape");
+    if (batch == 0 || batch > (1u << 24)) return fail(SFG_EINVAL, "mlp_backward: batch must be in [1, 2^24]");
+    if (!params || !dy || !workspace || (!grad && !dx)) return fail(SFG_EINVAL, "mlp_backward: NULL buffer");
+    Ws w = carve(net, batch, workspace);
+    if (workspace_bytes < w.total) return fail(SFG_ENOSPACE, "mlp_backward: workspace too small");
+    hipStream_t s = as_stream(stream);
+    const int B = (int)batch;
+    for (int l = net.L - 1; l >= 0; --l) {
+        const Layer &ly = net.layer[l];
+        const uint64_t n = (uint64_t)B * ly.out;
+        {
+            ProfScope _ps("mlp_elementwise", s);
+            // output layer: dZ = dy; hidden: dZ = dH * SiLU'(Z)
+            act_grad<<<grid_n(n), 256, 0, s>>>(l == net.L - 1 ? dy : w.dh, l == net.L - 1 ? nullptr : w.z[l], w.dz,
+                                                w.dzb, n);
+        }
+        if (grad) {
+            // dW[out][in] = dZb^T [out][B] * Xb [B][in]  (split over the batch)
+            gemm<true, false>(w.dzb, ly.out, w.xb[l], ly.in, w.part, ly.out, ly.in, B, kSplits, s);
+            ProfScope _ps("mlp_elementwise", s);
+            reduce_splits<<<grid_n((uint64_t)ly.out * ly.in), 256, 0, s>>>(w.part, kSplits, (uint64_t)ly.out * ly.in,
+                                                                            grad + ly.w_off);
+            col_sums<<<(ly.out + 255) / 256, 256, 0, s>>>(w.dz, B, ly.out, grad + ly.b_off);
+        }
+        if (l > 0 || dx) {
+            // dH[B][in] = dZb [B][out] * Wb [out][in]
+            float *target = (l > 0) ? w.dh : dx;
+            gemm<false, false>(w.dzb, ly.out, w.wb + ly.w_off, ly.in, target, B, ly.in, ly.out, 1, s);
+        }
+    }
+    return check_launch("mlp_backward");
+}
+
+extern "C" int mlp_mse_grad(uint32_t batch, uint32_t d_out, const float *y, const float *target, const float *mask,
+                            const float *col_weight, float *dy, float *loss, void *workspace, size_t workspace_bytes,
+                            void *stream) {
+    if (batch == 0 || d_out == 0) return fail(SFG_EINVAL, "mlp_mse_grad: empty batch");
+    if (!y || !target || !dy || !loss || !workspace) return fail(SFG_EINVAL, "mlp_mse_grad: NULL buffer");
+    if (workspace_bytes < (size_t)batch * 4) return fail(SFG_ENOSPACE, "mlp_mse_grad: workspace too small");
+    hipStream_t s = as_stream(stream);
+    float *rows = static_cast<float *>(workspace);
+    ProfScope _ps("mlp_elementwise", s);
+    mse_grad<<<(batch + 255) / 256, 256, 0, s>>>(y, target, mask, col_weight, (int)batch, (int)d_out, dy, rows);
+    sum_rows<<<1, 256, 0, s>>>(rows, (int)batch, loss);
+    return check_launch("mlp_mse_grad");
+}
+
+extern "C" int adam_step(uint64_t count, float *params, const float *grad, float *m, float *v, float lr, float beta1,
+                         float beta2, float eps, uint32_t step, void *stream) {
+    if (!params || !grad || !m || !v) return fail(SFG_EINVAL, "adam_step: NULL buffer");
+    if (step == 0) return fail(SFG_EINVAL, "adam_step: step counts from 1");
+    hipStream_t s = as_stream(stream);
+    const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+    ProfScope _ps("mlp_adam", s);
+    adam_kernel<<<grid_n(count), 256, 0, s>>>(count, params, grad, m, v, lr, beta1, beta2, eps, c1, c2);
+    return check_launch("adam_step");
+}

@@ -1,8 +1,10 @@
 // Parallel Barabasi-Albert generation (section "Parallel Barabasi-Albert (PBA)
-// method", Fig. 1) on one GPU.
+// method", Fig. 1) on one GPU, for one graph or a batch of graphs.
 //
 // The paper's processors become partitions of contiguous vertex blocks, and
-// its two message exchanges become on-device passes:
+// its two message exchanges become on-device passes.  A batch is a list of
+// graphs; every (graph, partition) pair is a segment, and all passes run over
+// all segments of the batch at once:
 //   draw1     phase 1: every slot j >= s of partition q is either terminal (a
 //             faction partition for j < s, or an inter-faction partition) or
 //             a pointer to a uniformly chosen earlier slot of q;
@@ -20,8 +22,8 @@
 //             written.
 //
 // Chains are resolved in memory: a workgroup follows pointers to their
-// terminal and writes the terminal back.  Partitions are bound to XCDs
-// (workgroup b runs on XCD b mod 8) and every XCD walks its partitions tile
+// terminal and writes the terminal back.  Segments are bound to XCDs
+// (workgroup b runs on XCD b mod 8) and every XCD walks its segments tile
 // by tile in slot order, so most pointers land in the already resolved,
 // L2-resident prefix of the partition and a chain costs about one load.
 // Output depends only on the draws, not on this schedule.
@@ -31,6 +33,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "pba.hpp"
 
 namespace sfg {
 namespace {
@@ -43,12 +46,36 @@ constexpr int kResItems = 4;
 constexpr int kResTile = kResThreads * kResItems;  // slots per resolve tile
 constexpr int kSubThreads = 256;
 constexpr uint32_t kMaxParts = 4096;
+constexpr uint32_t kMatchParts = 1024;  // LDS lane-match tables up to this many labels
+constexpr int kScanRows = 256;
 
 // Partition boundaries floor(q n / P), evaluated without 128-bit products.
 __host__ __device__ __forceinline__ uint64_t part_start(uint64_t q, uint64_t n, uint64_t P) {
     const uint64_t qd = n / P, r = n % P;
     return q * qd + (q * r) / P;
 }
+
+// One graph of a batch (device table; a single graph travels by value).
+struct PGraph {
+    uint64_t n, vbase, ebase, thr_p, H0;
+    uint32_t m, P, T1, CT, seg0;
+    uint32_t key0, key1, tag1, tag2;
+};
+
+// Segment -> graph.  A single graph has segments 0..P-1 and no table.
+struct Graphs {
+    const PGraph *table;      // null for a single graph
+    const uint32_t *seg_graph;
+    PGraph one;
+    __device__ __forceinline__ const PGraph &of_seg(uint32_t s, uint32_t &g) const {
+        if (!table) {
+            g = 0;
+            return one;
+        }
+        g = seg_graph[s];
+        return table[g];
+    }
+};
 
 struct Factions {
     // Ordered faction lists F(q) = fmem[foff[q] .. foff[q+1]) and the sorted
@@ -68,69 +95,91 @@ __device__ __forceinline__ uint32_t nonfaction(uint32_t r, const uint32_t *U, ui
     return x;
 }
 
+__device__ __forceinline__ uint32_t count_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
+}
+
+// ----------------------------------------------------------------------------- bases
+__global__ void pba_bases1(Graphs G, uint32_t S, uint64_t total, uint64_t *base1) {
+    const uint32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > S) return;
+    if (s == S) {
+        base1[S] = total;
+        return;
+    }
+    uint32_t g;
+    const PGraph &p = G.of_seg(s, g);
+    base1[s] = p.ebase + (uint64_t)p.m * part_start(s - p.seg0, p.n, p.P);
+}
+
 // ----------------------------------------------------------------------------- phase 1 draw
 struct Draw1Args {
-    uint64_t n, P;
-    uint32_t m;
-    uint32_t key0, key1, tagword;
-    uint64_t thr_p;  // inter-faction threshold in [0, 2^32]
+    Graphs G;
+    const uint64_t *base1;
+    uint32_t chunks;  // workgroups per segment
     Factions f;
     uint32_t *lab;
 };
 
 __global__ __launch_bounds__(kDrawThreads) void pba_draw1(Draw1Args a) {
-    const uint32_t q = blockIdx.y;
-    const uint64_t s0 = part_start(q, a.n, a.P), s1 = part_start(q + 1, a.n, a.P);
-    const uint64_t nslots = (s1 - s0) * a.m;
-    uint32_t s = 1, u = 1, self = q;
+    const uint32_t s = blockIdx.x / a.chunks, c = blockIdx.x % a.chunks;
+    uint32_t g;
+    const PGraph &p = a.G.of_seg(s, g);
+    const uint32_t q = s - p.seg0;
+    const uint64_t b0 = a.base1[s], nslots = a.base1[s + 1] - b0;
+    uint32_t fs = 1, u = 1, self = q;
     const uint32_t *F = &self, *U = &self;
     if (a.f.foff) {
         F = a.f.fmem + a.f.foff[q];
-        s = a.f.foff[q + 1] - a.f.foff[q];
+        fs = a.f.foff[q + 1] - a.f.foff[q];
         U = a.f.umem + a.f.uoff[q];
         u = a.f.uoff[q + 1] - a.f.uoff[q];
     }
-    const uint32_t nnf = (uint32_t)a.P - u;
-    const uint64_t stride = (uint64_t)gridDim.x * kDrawThreads;
-    for (uint64_t j = (uint64_t)blockIdx.x * kDrawThreads + threadIdx.x; j < nslots; j += stride) {
+    const uint32_t nnf = p.P - u;
+    const uint64_t stride = (uint64_t)a.chunks * kDrawThreads;
+    for (uint64_t j = (uint64_t)c * kDrawThreads + threadIdx.x; j < nslots; j += stride) {
         uint32_t enc;
-        if (j < s) {
+        if (j < fs) {
             enc = kTerm | F[j];
         } else {
-            const Block4 w = philox((uint32_t)j, (uint32_t)(j >> 32), q, a.tagword, a.key0, a.key1);
+            const Block4 w = philox((uint32_t)j, (uint32_t)(j >> 32), q, p.tag1, p.key0, p.key1);
             const uint64_t U64 = make_u64(w.w1, w.w2);
-            if (nnf > 0 && (uint64_t)w.w0 < a.thr_p)
+            if (nnf > 0 && (uint64_t)w.w0 < p.thr_p)
                 enc = kTerm | nonfaction((uint32_t)uidx64(U64, nnf), U, u);
             else
                 enc = (uint32_t)uidx64(U64, j);  // copy an earlier slot
         }
-        a.lab[s0 * a.m + j] = enc;
+        a.lab[b0 + j] = enc;
     }
 }
 
 // ----------------------------------------------------------------------------- phase 2 draw
 struct Draw2Args {
-    uint64_t n, P, total;
-    uint32_t key0, key1, tagword;
-    const uint64_t *sbase;  // [P+1] list bases (prefix of D)
+    Graphs G;
+    uint32_t S;
+    uint64_t total;
+    const uint64_t *sbase;  // [S+1] list bases (prefix of D)
     uint32_t *sel;
 };
 
-__device__ __forceinline__ void pba_draw2_one(const Draw2Args &a, uint64_t g) {
-    // partition l with sbase[l] <= g < sbase[l+1]
-    uint32_t lo = 0, hi = (uint32_t)a.P;
+__device__ __forceinline__ void pba_draw2_one(const Draw2Args &a, uint64_t gi) {
+    // segment s with sbase[s] <= gi < sbase[s+1]
+    uint32_t lo = 0, hi = a.S;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) / 2;
-        if (a.sbase[mid] <= g)
+        if (a.sbase[mid] <= gi)
             lo = mid;
         else
             hi = mid;
     }
-    const uint32_t l = lo;
-    const uint64_t t = g - a.sbase[l];
-    const uint64_t D = a.sbase[l + 1] - a.sbase[l];
-    const uint64_t L = part_start(l + 1, a.n, a.P) - part_start(l, a.n, a.P);
-    const Block4 w = philox((uint32_t)t, (uint32_t)(t >> 32), l, a.tagword, a.key0, a.key1);
+    const uint32_t s = lo;
+    uint32_t g;
+    const PGraph &p = a.G.of_seg(s, g);
+    const uint32_t l = s - p.seg0;
+    const uint64_t t = gi - a.sbase[s];
+    const uint64_t D = a.sbase[s + 1] - a.sbase[s];
+    const uint64_t L = part_start(l + 1, p.n, p.P) - part_start(l, p.n, p.P);
+    const Block4 w = philox((uint32_t)t, (uint32_t)(t >> 32), l, p.tag2, p.key0, p.key1);
     // Pool entry r of the first 2 + 2t: the seed clique (0, 1), an arrival
     // vertex floor(t' L / D) at even r, or the endpoint of selection t' at odd r.
     const uint64_t r = uidx64(make_u64(w.w0, w.w1), 2 + 2 * t);
@@ -143,26 +192,26 @@ __device__ __forceinline__ void pba_draw2_one(const Draw2Args &a, uint64_t g) {
     } else {
         enc = (uint32_t)((r - 3) >> 1);
     }
-    a.sel[g] = enc;
+    a.sel[gi] = enc;
 }
 
 __global__ __launch_bounds__(kDrawThreads) void pba_draw2(Draw2Args a) {
     const uint64_t stride = (uint64_t)gridDim.x * kDrawThreads;
-    for (uint64_t g = (uint64_t)blockIdx.x * kDrawThreads + threadIdx.x; g < a.total; g += stride)
-        pba_draw2_one(a, g);
+    for (uint64_t gi = (uint64_t)blockIdx.x * kDrawThreads + threadIdx.x; gi < a.total; gi += stride)
+        pba_draw2_one(a, gi);
 }
 
 // ----------------------------------------------------------------------------- chain resolution
-// Segment q spans enc[base[q] .. base[q+1]); pointers are segment-local.
-// Tiles of segment q are queued on XCD q mod 8, segment by segment, in order.
+// Segment s spans enc[base[s] .. base[s+1]); pointers are segment-local.
+// Tiles of segment s are queued on XCD s mod 8, segment by segment, in order.
 struct ResolveArgs {
     uint32_t *enc;
-    const uint64_t *base;     // [P+1]
+    const uint64_t *base;     // [S+1]
     const uint64_t *xprefix;  // [8][xstride] tile prefix per XCD queue
     const uint64_t *xtotal;   // [8]
     uint32_t *queues;         // [8] tile tickets
     uint32_t *err;
-    uint32_t P, xstride;
+    uint32_t S, xstride;
 };
 
 __global__ __launch_bounds__(kResThreads) void pba_resolve(ResolveArgs a) {
@@ -174,7 +223,7 @@ __global__ __launch_bounds__(kResThreads) void pba_resolve(ResolveArgs a) {
         const uint32_t x = (home + att) % kXcd;
         const uint64_t total = a.xtotal[x];
         const uint64_t *pre = a.xprefix + (uint64_t)x * a.xstride;
-        const uint32_t nseg = (a.P > x) ? (a.P - x + kXcd - 1) / kXcd : 0;
+        const uint32_t nseg = (a.S > x) ? (a.S - x + kXcd - 1) / kXcd : 0;
         for (;;) {
             if (tid == 0) {
                 const uint64_t t = fetch_add_agent(&a.queues[x], 1u);
@@ -197,9 +246,9 @@ __global__ __launch_bounds__(kResThreads) void pba_resolve(ResolveArgs a) {
             const uint32_t i = s_seg;
             __syncthreads();
             if (t >= total) break;
-            const uint32_t q = x + kXcd * i;
-            const uint64_t b0 = a.base[q];
-            const uint64_t len = a.base[q + 1] - b0;
+            const uint32_t sg = x + kXcd * i;
+            const uint64_t b0 = a.base[sg];
+            const uint64_t len = a.base[sg + 1] - b0;
             const uint64_t first = (t - pre[i]) * kResTile;
             uint32_t *seg = a.enc + b0;
 #pragma unroll
@@ -229,55 +278,92 @@ __global__ __launch_bounds__(kResThreads) void pba_resolve(ResolveArgs a) {
 }
 
 // Per-XCD queues of resolve tiles: prefix of tile counts over the segments
-// q = x, x+8, ... of each XCD x.
-__global__ void pba_tile_table(const uint64_t *base, uint32_t P, uint32_t xstride, uint64_t *xprefix,
-                               uint64_t *xtotal, uint32_t *queues) {
-    const uint32_t x = threadIdx.x;
-    if (x >= kXcd) return;
+// s = x, x+8, ... of each XCD x (one workgroup per XCD queue).
+__global__ __launch_bounds__(1024) void pba_tile_table(const uint64_t *base, uint32_t S, uint32_t xstride,
+                                                       uint64_t *xprefix, uint64_t *xtotal, uint32_t *queues) {
+    __shared__ uint64_t sm[1024];
+    const uint32_t x = blockIdx.x;
+    const uint32_t nseg = S > x ? (S - x + kXcd - 1) / kXcd : 0;
+    const uint32_t per = (nseg + 1023) / 1024;
+    const uint32_t lo = threadIdx.x * per, hi = std::min<uint32_t>(nseg, lo + per);
     uint64_t acc = 0;
-    uint32_t i = 0;
-    for (uint32_t q = x; q < P; q += kXcd, ++i) {
-        xprefix[(uint64_t)x * xstride + i] = acc;
-        acc += (base[q + 1] - base[q] + kResTile - 1) / kResTile;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t sg = x + kXcd * i;
+        acc += (base[sg + 1] - base[sg] + kResTile - 1) / kResTile;
     }
-    xprefix[(uint64_t)x * xstride + i] = acc;
-    xtotal[x] = acc;
-    queues[x] = 0;
-}
-
-__global__ void pba_phase1_bases(uint64_t n, uint64_t P, uint32_t m, uint64_t *base) {
-    const uint64_t q = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q <= P) base[q] = part_start(q, n, P) * m;
+    sm[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint64_t o = threadIdx.x >= (uint32_t)off ? sm[threadIdx.x - off] : 0;
+        __syncthreads();
+        sm[threadIdx.x] += o;
+        __syncthreads();
+    }
+    uint64_t run = threadIdx.x > 0 ? sm[threadIdx.x - 1] : 0;
+    uint64_t *pre = xprefix + (uint64_t)x * xstride;
+    for (uint32_t i = lo; i < hi; ++i) {
+        pre[i] = run;
+        const uint32_t sg = x + kXcd * i;
+        run += (base[sg + 1] - base[sg] + kResTile - 1) / kResTile;
+    }
+    if (threadIdx.x == 1023) {
+        pre[nseg] = sm[1023];
+        xtotal[x] = sm[1023];
+        queues[x] = 0;
+    }
 }
 
 // ----------------------------------------------------------------------------- counting
-// Tile (q, tau) covers slots [tau * CT, (tau+1) * CT) of partition q; its
-// label histogram is row (q * T1 + tau) of H (P columns).
+// Tile (q, tau) of graph g covers slots [tau * CT, (tau+1) * CT) of partition
+// q; its label histogram is row H0 + (q * T1 + tau) of P columns.
 struct CountArgs {
+    Graphs G;
     const uint32_t *lab;
-    const uint64_t *base1;  // phase-1 bases [P+1]
+    const uint64_t *base1;
     uint32_t *H;
-    uint32_t P, T1, CT;
+    uint32_t T1max;
 };
 
 __global__ __launch_bounds__(256) void pba_count(CountArgs a) {
     extern __shared__ uint32_t s_h[];  // [P]
-    const uint32_t q = blockIdx.y, tau = blockIdx.x;
-    for (uint32_t l = threadIdx.x; l < a.P; l += 256) s_h[l] = 0;
+    const uint32_t s = blockIdx.x / a.T1max, tau = blockIdx.x % a.T1max;
+    uint32_t g;
+    const PGraph &p = a.G.of_seg(s, g);
+    if (tau >= p.T1) return;
+    const uint32_t q = s - p.seg0;
+    for (uint32_t l = threadIdx.x; l < p.P; l += 256) s_h[l] = 0;
     __syncthreads();
-    const uint64_t b0 = a.base1[q], len = a.base1[q + 1] - b0;
-    const uint64_t first = (uint64_t)tau * a.CT;
-    const uint64_t last = std::min<uint64_t>(len, first + a.CT);
+    const uint64_t b0 = a.base1[s], len = a.base1[s + 1] - b0;
+    const uint64_t first = (uint64_t)tau * p.CT;
+    const uint64_t last = std::min<uint64_t>(len, first + p.CT);
     for (uint64_t j = first + threadIdx.x; j < last; j += 256) atomicAdd(&s_h[a.lab[b0 + j] & ~kTerm], 1u);
     __syncthreads();
-    uint32_t *row = a.H + ((uint64_t)q * a.T1 + tau) * a.P;
-    for (uint32_t l = threadIdx.x; l < a.P; l += 256) row[l] = s_h[l];
+    uint32_t *row = a.H + p.H0 + ((uint64_t)q * p.T1 + tau) * p.P;
+    for (uint32_t l = threadIdx.x; l < p.P; l += 256) row[l] = s_h[l];
 }
 
-// Column-wise exclusive scan of H (R rows x P columns) in three steps over
-// groups of kScanRows rows.
-constexpr int kScanRows = 256;
+// Column-wise exclusive scan of every graph's H block.  Column c of the batch
+// is label c - seg0 of the graph owning segment c; D[c] receives its total.
+__global__ __launch_bounds__(256) void pba_scan_columns(Graphs G, uint32_t S, uint32_t *H, uint64_t *D,
+                                                        uint32_t *err) {
+    const uint32_t c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= S) return;
+    uint32_t g;
+    const PGraph &p = G.of_seg(c, g);
+    const uint32_t l = c - p.seg0;
+    const uint64_t rows = (uint64_t)p.P * p.T1;
+    uint32_t *col = H + p.H0 + l;
+    uint64_t acc = 0;
+    for (uint64_t r = 0; r < rows; ++r) {
+        const uint32_t v = col[r * p.P];
+        col[r * p.P] = (uint32_t)acc;
+        acc += v;
+    }
+    D[c] = acc;
+    if (acc >= kTerm) raise_device_error(err, DEVERR_QUEUE);  // a list longer than 2^31 is unsupported
+}
 
+// The same scan for one large graph, in three steps over groups of rows.
 __global__ __launch_bounds__(256) void pba_scan_partial(const uint32_t *H, uint64_t R, uint32_t P, uint32_t *part) {
     const uint32_t col = blockIdx.y * 256 + threadIdx.x;
     if (col >= P) return;
@@ -299,7 +385,7 @@ __global__ __launch_bounds__(256) void pba_scan_groups(uint32_t *part, uint64_t 
         acc += c;
     }
     D[col] = acc;
-    if (acc >= kTerm) raise_device_error(err, DEVERR_QUEUE);  // a list longer than 2^31 is unsupported
+    if (acc >= kTerm) raise_device_error(err, DEVERR_QUEUE);
 }
 
 __global__ __launch_bounds__(256) void pba_scan_apply(uint32_t *H, uint64_t R, uint32_t P, const uint32_t *part) {
@@ -315,68 +401,76 @@ __global__ __launch_bounds__(256) void pba_scan_apply(uint32_t *H, uint64_t R, u
     }
 }
 
-// List bases: sbase = exclusive prefix of D (single block).
-__global__ __launch_bounds__(1024) void pba_list_bases(const uint64_t *D, uint32_t P, uint64_t *sbase) {
-    __shared__ uint64_t s[1024];
-    const uint32_t per = (P + 1023) / 1024;
-    const uint32_t lo = threadIdx.x * per, hi = std::min<uint32_t>(P, lo + per);
+// List bases: sbase = exclusive prefix of D over all segments (single block).
+__global__ __launch_bounds__(1024) void pba_list_bases(const uint64_t *D, uint32_t S, uint64_t *sbase) {
+    __shared__ uint64_t sm[1024];
+    const uint32_t per = (S + 1023) / 1024;
+    const uint32_t lo = threadIdx.x * per, hi = std::min<uint32_t>(S, lo + per);
     uint64_t acc = 0;
     for (uint32_t i = lo; i < hi; ++i) acc += D[i];
-    s[threadIdx.x] = acc;
+    sm[threadIdx.x] = acc;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        const uint64_t o = threadIdx.x >= (uint32_t)off ? s[threadIdx.x - off] : 0;
+        const uint64_t o = threadIdx.x >= (uint32_t)off ? sm[threadIdx.x - off] : 0;
         __syncthreads();
-        s[threadIdx.x] += o;
+        sm[threadIdx.x] += o;
         __syncthreads();
     }
-    uint64_t run = threadIdx.x > 0 ? s[threadIdx.x - 1] : 0;
+    uint64_t run = threadIdx.x > 0 ? sm[threadIdx.x - 1] : 0;
     for (uint32_t i = lo; i < hi; ++i) {
         sbase[i] = run;
         run += D[i];
     }
-    if (threadIdx.x == 1023) sbase[P] = s[1023];
+    if (threadIdx.x == 1023) sbase[S] = sm[1023];
 }
 
 // ----------------------------------------------------------------------------- substitution
 // Tile (q, tau) of CT slots: 4 waves each walk a contiguous quarter in slot
 // order.  The k-th occurrence of label l in the tile takes endpoint
-// H[q,tau][l] + k of l's list (H holds the exclusive column prefix).
+// H[q,tau][l] + k of l's list (H holds the exclusive column prefix).  Lanes of
+// one 64-slot step that share a label are found through an LDS lane-match
+// table (MATCH, up to kMatchParts labels) or by ballots over the label bits.
 struct SubArgs {
-    uint64_t n, P;
-    uint32_t m, T1, CT, lbits;
+    Graphs G;
     const uint32_t *lab;
     const uint64_t *base1;
     const uint32_t *H;
     const uint64_t *sbase;
     const uint32_t *sel;
     void *src, *dst;
+    uint32_t T1max, Pmax;
 };
 
-__device__ __forceinline__ uint32_t count_below(uint64_t mask) {
-    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0));
-}
-
-template <typename IdT> __global__ __launch_bounds__(kSubThreads) void pba_substitute(SubArgs a) {
-    extern __shared__ uint32_t s_cnt[];  // [4][P]
-    const uint32_t q = blockIdx.y, tau = blockIdx.x;
+template <typename IdT, bool MATCH> __global__ __launch_bounds__(kSubThreads) void pba_substitute(SubArgs a) {
+    extern __shared__ uint64_t s_dyn[];  // MATCH: [4][Pmax] masks, then [4][Pmax] counters
+    const uint32_t s = blockIdx.x / a.T1max, tau = blockIdx.x % a.T1max;
+    uint32_t g;
+    const PGraph &p = a.G.of_seg(s, g);
+    if (tau >= p.T1) return;
+    const uint32_t q = s - p.seg0;
     const int tid = threadIdx.x, w = tid >> 6;
     const uint32_t lane = tid & 63;
-    const uint32_t P = (uint32_t)a.P;
-    for (uint32_t i = tid; i < 4 * P; i += kSubThreads) s_cnt[i] = 0;
+    const uint32_t P = p.P;
+    uint64_t *s_match = s_dyn;
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn + (MATCH ? 4 * a.Pmax : 0));
+    for (uint32_t i = tid; i < 4 * P; i += kSubThreads) {
+        s_cnt[i] = 0;
+        if (MATCH) s_match[i] = 0;
+    }
     __syncthreads();
-    const uint64_t b0 = a.base1[q], len = a.base1[q + 1] - b0;
-    const uint64_t first = (uint64_t)tau * a.CT;
-    const uint64_t last = std::min<uint64_t>(len, first + a.CT);
-    const uint32_t quarter = a.CT / 4;
+    const uint64_t b0 = a.base1[s], len = a.base1[s + 1] - b0;
+    const uint64_t first = (uint64_t)tau * p.CT;
+    const uint64_t last = std::min<uint64_t>(len, first + p.CT);
+    const uint32_t quarter = p.CT / 4;
     const uint64_t wfirst = first + (uint64_t)w * quarter;
     const uint64_t wlast = std::min<uint64_t>(last, wfirst + quarter);
     uint32_t *cnt = s_cnt + (uint64_t)w * P;
+    uint64_t *match = s_match + (uint64_t)w * P;
     // Pass 1: per-wave label counts.
     for (uint64_t j = wfirst + lane; j < wlast; j += 64) atomicAdd(&cnt[a.lab[b0 + j] & ~kTerm], 1u);
     __syncthreads();
     // Per label: start of each wave's run inside the tile's share of the list.
-    const uint32_t *hrow = a.H + ((uint64_t)q * a.T1 + tau) * P;
+    const uint32_t *hrow = a.H + p.H0 + ((uint64_t)q * p.T1 + tau) * P;
     for (uint32_t l = tid; l < P; l += kSubThreads) {
         uint32_t acc = hrow[l];
         for (int wv = 0; wv < 4; ++wv) {
@@ -386,41 +480,45 @@ template <typename IdT> __global__ __launch_bounds__(kSubThreads) void pba_subst
         }
     }
     __syncthreads();
-    // Pass 2: slots in order; equal labels in a 64-slot step are ranked by lane.
-    const uint64_t vstart = part_start(q, a.n, a.P);
+    // Pass 2: slots in order.
+    uint32_t lbits = 0;
+    while ((1u << lbits) < P) ++lbits;
+    const uint64_t vstart = p.vbase + part_start(q, p.n, p.P);
     IdT *src = static_cast<IdT *>(a.src), *dst = static_cast<IdT *>(a.dst);
+    const uint64_t *lbase = a.sbase + p.seg0;
     for (uint64_t j0 = wfirst; j0 < wlast; j0 += 64) {
         const uint64_t j = j0 + lane;
         const bool valid = j < wlast;
         const uint32_t l = valid ? (a.lab[b0 + j] & ~kTerm) : 0;
-        uint64_t peers = __ballot(valid);
-        for (uint32_t b = 0; b < a.lbits; ++b) {
-            const bool bit = (l >> b) & 1u;
-            const uint64_t bb = __ballot(bit);
-            peers &= bit ? bb : ~bb;
+        uint64_t peers;
+        if (MATCH) {
+            if (valid) atomicOr(reinterpret_cast<unsigned long long *>(&match[l]), 1ull << lane);
+            __builtin_amdgcn_wave_barrier();
+            peers = valid ? match[l] : 0ull;
+        } else {
+            peers = __ballot(valid);
+            for (uint32_t b = 0; b < lbits; ++b) {
+                const bool bit = (l >> b) & 1u;
+                const uint64_t bb = __ballot(bit);
+                peers &= bit ? bb : ~bb;
+            }
+        }
+        const uint32_t below = count_below(peers);
+        const uint32_t k = cnt[l];
+        __builtin_amdgcn_wave_barrier();
+        if (valid && below == 0) {
+            cnt[l] = k + (uint32_t)__popcll(peers);
+            if (MATCH) match[l] = 0;
         }
         if (valid) {
-            const uint32_t below = count_below(peers);
-            const uint32_t k = cnt[l];
-            if (below == 0) cnt[l] = k + (uint32_t)__popcll(peers);
-            const uint64_t idx = a.sbase[l] + k + below;
-            const uint64_t y = a.sel[idx] & ~kTerm;
+            const uint64_t y = a.sel[lbase[l] + k + below] & ~kTerm;
             const uint64_t e = b0 + j;
-            src[e] = (IdT)(vstart + j / a.m);
-            dst[e] = (IdT)(part_start(l, a.n, a.P) + y);
+            src[e] = (IdT)(vstart + j / p.m);
+            dst[e] = (IdT)(p.vbase + part_start(l, p.n, p.P) + y);
         }
         __builtin_amdgcn_wave_barrier();
     }
 }
-
-// ----------------------------------------------------------------------------- host
-struct Plan {
-    uint64_t n, E, P, Lmax;
-    uint32_t m, T1, CT, xstride;
-    uint64_t R, groups;
-    size_t off_lab, off_sel, off_H, off_part, off_base1, off_sbase, off_D, off_xpre, off_xtot, off_queues,
-        off_foff, off_fmem, off_uoff, off_umem, total;
-};
 
 uint32_t choose_ct(uint64_t P) {
     // Tiles of the count/substitution passes: large enough that the P x P
@@ -430,19 +528,35 @@ uint32_t choose_ct(uint64_t P) {
     return ct;
 }
 
-Plan make_plan(uint64_t n, uint32_t m, uint32_t P, uint64_t fmem_count) {
-    Plan p;
+}  // namespace
+
+// ----------------------------------------------------------------------------- host
+// Layout of a batch in the workspace.
+struct PbaPlan {
+    uint32_t count, S, T1max, Pmax, xstride;
+    uint64_t E, Htotal, groups;
+    bool grouped;  // one large graph: three-step column scan
+    size_t off_lab, off_sel, off_H, off_part, off_base1, off_sbase, off_D, off_xpre, off_xtot, off_queues, off_foff,
+        off_fmem, off_uoff, off_umem, off_table, off_seg, total;
+};
+
+static PbaPlan plan_batch(const PbaGraphSpec *gs, uint32_t count, uint64_t fmem_count) {
+    PbaPlan p;
     memset(&p, 0, sizeof(p));
-    p.n = n;
-    p.m = m;
-    p.P = P;
-    p.E = n * m;
-    p.Lmax = (n + P - 1) / P;
-    p.CT = choose_ct(P);
-    p.T1 = (uint32_t)((p.Lmax * m + p.CT - 1) / p.CT);
-    p.R = (uint64_t)P * p.T1;
-    p.groups = (p.R + kScanRows - 1) / kScanRows;
-    p.xstride = (P + kXcd - 1) / kXcd + 1;
+    p.count = count;
+    for (uint32_t g = 0; g < count; ++g) {
+        const uint64_t Lmax = (gs[g].n + gs[g].P - 1) / gs[g].P;
+        const uint32_t CT = choose_ct(gs[g].P);
+        const uint32_t T1 = (uint32_t)((Lmax * gs[g].m + CT - 1) / CT);
+        p.S += gs[g].P;
+        p.E += gs[g].n * gs[g].m;
+        p.Htotal += (uint64_t)gs[g].P * T1 * gs[g].P;
+        p.T1max = std::max(p.T1max, T1);
+        p.Pmax = std::max(p.Pmax, gs[g].P);
+        if (count == 1) p.groups = ((uint64_t)gs[g].P * T1 + kScanRows - 1) / kScanRows;
+    }
+    p.grouped = count == 1 && p.groups > 16;
+    p.xstride = (p.S + kXcd - 1) / kXcd + 1;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t r = o;
@@ -451,68 +565,70 @@ Plan make_plan(uint64_t n, uint32_t m, uint32_t P, uint64_t fmem_count) {
     };
     p.off_lab = take(p.E * 4);
     p.off_sel = take(p.E * 4);
-    p.off_H = take(p.R * P * 4);
-    p.off_part = take(p.groups * P * 4);
-    p.off_base1 = take((P + 1) * 8);
-    p.off_sbase = take((P + 1) * 8);
-    p.off_D = take(P * 8);
+    p.off_H = take(p.Htotal * 4);
+    p.off_part = take(p.grouped ? p.groups * p.Pmax * 4 : 0);
+    p.off_base1 = take((p.S + 1) * 8);
+    p.off_sbase = take((p.S + 1) * 8);
+    p.off_D = take(p.S * 8);
     p.off_xpre = take((size_t)kXcd * p.xstride * 8);
     p.off_xtot = take(kXcd * 8);
     p.off_queues = take(2 * kXcd * 4);
-    p.off_foff = take((P + 1) * 4);
-    p.off_fmem = take(std::max<uint64_t>(fmem_count, 1) * 4);
-    p.off_uoff = take((P + 1) * 4);
-    p.off_umem = take(std::max<uint64_t>(fmem_count, 1) * 4);
+    p.off_foff = take(count == 1 ? (p.S + 1) * 4 : 0);
+    p.off_fmem = take(count == 1 ? std::max<uint64_t>(fmem_count, 1) * 4 : 0);
+    p.off_uoff = take(count == 1 ? (p.S + 1) * 4 : 0);
+    p.off_umem = take(count == 1 ? std::max<uint64_t>(fmem_count, 1) * 4 : 0);
+    p.off_table = take(count > 1 ? count * sizeof(PGraph) : 0);
+    p.off_seg = take(count > 1 ? p.S * 4 : 0);
     p.total = o;
     return p;
 }
 
-}  // namespace
-}  // namespace sfg
+size_t pba_batch_workspace_bytes(const PbaGraphSpec *gs, uint32_t count) { return plan_batch(gs, count, 0).total; }
 
-using namespace sfg;
-
-extern "C" size_t pba_workspace_bytes(uint64_t n, uint32_t m, uint32_t num_parts, uint64_t num_faction_members) {
-    if (num_parts == 0 || m == 0 || n == 0) return 0;
-    return make_plan(n, m, num_parts, num_faction_members).total;
+int pba_check_spec(const PbaGraphSpec &g, int id_bytes, const char *who) {
+    if (g.m == 0) return fail(SFG_EINVAL, "%s: m must be >= 1", who);
+    if (g.P == 0 || g.P > kMaxParts) return fail(SFG_EINVAL, "%s: num_parts must be in [1, %u]", who, kMaxParts);
+    if (g.n < 2ull * g.P) return fail(SFG_EINVAL, "%s: every partition needs >= 2 vertices (n >= 2 * num_parts)", who);
+    if (!(g.p_inter >= 0.0 && g.p_inter <= 1.0)) return fail(SFG_EINVAL, "%s: p_inter must be in [0, 1]", who);
+    if (g.graph_id >= (1u << 24)) return fail(SFG_EINVAL, "%s: graph_id must be < 2^24", who);
+    if (g.n > (1ull << 40) || (uint64_t)g.m > (1ull << 20) || g.n * g.m > (1ull << 46))
+        return fail(SFG_ERANGE, "%s: n * m too large", who);
+    if (id_bytes == 4 && g.vbase + g.n - 1 > 0x7FFFFFFFull) return fail(SFG_ERANGE, "%s: ids do not fit int32", who);
+    const uint64_t Lmax = (g.n + g.P - 1) / g.P;
+    if (Lmax * g.m >= kTerm) return fail(SFG_ERANGE, "%s: a partition holds >= 2^31 slots", who);
+    // floor(t L / D) in 64 bits needs D * L < 2^64 with D <= n m.
+    if ((unsigned __int128)(g.n * g.m) * Lmax >= ((unsigned __int128)1 << 64))
+        return fail(SFG_ERANGE, "%s: n * m * ceil(n / P) must be < 2^64", who);
+    return SFG_OK;
 }
 
-extern "C" int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p_inter, const uint32_t *faction_off,
-                            const uint32_t *faction_members, uint64_t seed, uint32_t graph_id, int id_bytes, void *src,
-                            void *dst, void *workspace, size_t workspace_bytes, void *stream) {
-    const uint32_t P = num_parts;
-    if (m == 0) return fail(SFG_EINVAL, "pba_generate: m must be >= 1");
-    if (P == 0 || P > kMaxParts) return fail(SFG_EINVAL, "pba_generate: num_parts must be in [1, %u]", kMaxParts);
-    if (n < 2ull * P) return fail(SFG_EINVAL, "pba_generate: every partition needs >= 2 vertices (n >= 2 * num_parts)");
-    if (!(p_inter >= 0.0 && p_inter <= 1.0)) return fail(SFG_EINVAL, "pba_generate: p_inter must be in [0, 1]");
-    if (id_bytes != 4 && id_bytes != 8) return fail(SFG_EINVAL, "pba_generate: id_bytes must be 4 or 8");
-    if (graph_id >= (1u << 24)) return fail(SFG_EINVAL, "pba_generate: graph_id must be < 2^24");
-    if (!src || !dst || !workspace) return fail(SFG_EINVAL, "pba_generate: NULL buffer");
-    if (n > (1ull << 40) || (uint64_t)m > (1ull << 20) || n * m > (1ull << 46))
-        return fail(SFG_ERANGE, "pba_generate: n * m too large");
-    if (id_bytes == 4 && n - 1 > 0x7FFFFFFFull) return fail(SFG_ERANGE, "pba_generate: n does not fit int32 ids");
-    const uint64_t Lmax = (n + P - 1) / P;
-    if (Lmax * m >= kTerm) return fail(SFG_ERANGE, "pba_generate: a partition holds >= 2^31 slots");
-    // floor(t L / D) in 64 bits needs D * L < 2^64 with D <= n m.
-    if ((unsigned __int128)(n * m) * Lmax >= ((unsigned __int128)1 << 64))
-        return fail(SFG_ERANGE, "pba_generate: n * m * ceil(n / P) must be < 2^64");
+int pba_run_batch(const PbaGraphSpec *gs, uint32_t count, const uint32_t *faction_off, const uint32_t *faction_members,
+                  int id_bytes, void *src, void *dst, void *workspace, size_t workspace_bytes, hipStream_t s) {
+    const char *who = count == 1 ? "pba_generate" : "ensemble_generate";
+    if (count == 0) return SFG_OK;
+    for (uint32_t g = 0; g < count; ++g) {
+        int rc = pba_check_spec(gs[g], id_bytes, who);
+        if (rc != SFG_OK) return rc;
+    }
+    if (faction_off && count != 1) return fail(SFG_EINVAL, "%s: faction tables need a single graph", who);
     // Faction tables.
     std::vector<uint32_t> foff, fmem, uoff, umem;
     if (faction_off) {
-        if (faction_off[0] != 0) return fail(SFG_EINVAL, "pba_generate: faction_off[0] must be 0");
+        const uint32_t P = gs[0].P;
+        if (faction_off[0] != 0) return fail(SFG_EINVAL, "%s: faction_off[0] must be 0", who);
         for (uint32_t q = 0; q < P; ++q) {
-            if (faction_off[q + 1] < faction_off[q]) return fail(SFG_EINVAL, "pba_generate: faction_off is not monotone");
+            if (faction_off[q + 1] < faction_off[q]) return fail(SFG_EINVAL, "%s: faction_off is not monotone", who);
             // Copying needs an earlier slot: every partition starts from at
             // least one faction member.
             if (faction_off[q + 1] == faction_off[q])
-                return fail(SFG_EINVAL, "pba_generate: partition %u has an empty faction list", q);
+                return fail(SFG_EINVAL, "%s: partition %u has an empty faction list", who, q);
         }
         const uint32_t total = faction_off[P];
-        if (total > 0 && !faction_members) return fail(SFG_EINVAL, "pba_generate: faction_members is NULL");
+        if (total > 0 && !faction_members) return fail(SFG_EINVAL, "%s: faction_members is NULL", who);
         foff.assign(faction_off, faction_off + P + 1);
         fmem.assign(faction_members, faction_members + total);
         for (uint32_t i = 0; i < total; ++i)
-            if (fmem[i] >= P) return fail(SFG_EINVAL, "pba_generate: faction member %u >= num_parts", fmem[i]);
+            if (fmem[i] >= P) return fail(SFG_EINVAL, "%s: faction member %u >= num_parts", who, fmem[i]);
         uoff.resize(P + 1);
         uoff[0] = 0;
         for (uint32_t q = 0; q < P; ++q) {
@@ -523,14 +639,13 @@ extern "C" int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p
             uoff[q + 1] = (uint32_t)umem.size();
         }
     }
-    Plan pl = make_plan(n, m, P, fmem.size());
+    const PbaPlan pl = plan_batch(gs, count, fmem.size());
+    if (!src || !dst || !workspace) return fail(SFG_EINVAL, "%s: NULL buffer", who);
     if (workspace_bytes < pl.total)
-        return fail(SFG_ENOSPACE, "pba_generate: workspace has %zu bytes, needs %zu", workspace_bytes, pl.total);
-    const size_t lds_sub = (size_t)4 * P * 4;
+        return fail(SFG_ENOSPACE, "%s: workspace has %zu bytes, needs %zu", who, workspace_bytes, pl.total);
     uint32_t *err = device_error_word();
-    if (!err) return fail(SFG_EDEVICE, "pba_generate: no device");
+    if (!err) return fail(SFG_EDEVICE, "%s: no device", who);
 
-    hipStream_t s = as_stream(stream);
     char *ws = static_cast<char *>(workspace);
     uint32_t *lab = reinterpret_cast<uint32_t *>(ws + pl.off_lab);
     uint32_t *sel = reinterpret_cast<uint32_t *>(ws + pl.off_sel);
@@ -542,6 +657,52 @@ extern "C" int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p
     uint64_t *xpre = reinterpret_cast<uint64_t *>(ws + pl.off_xpre);
     uint64_t *xtot = reinterpret_cast<uint64_t *>(ws + pl.off_xtot);
     uint32_t *queues = reinterpret_cast<uint32_t *>(ws + pl.off_queues);
+
+    // Graph table.
+    std::vector<PGraph> table(count);
+    std::vector<uint32_t> seg_graph;
+    uint64_t ebase = 0, H0 = 0;
+    uint32_t seg0 = 0;
+    for (uint32_t g = 0; g < count; ++g) {
+        const PbaGraphSpec &sp = gs[g];
+        PGraph &p = table[g];
+        memset(&p, 0, sizeof(p));
+        const uint64_t Lmax = (sp.n + sp.P - 1) / sp.P;
+        p.n = sp.n;
+        p.vbase = sp.vbase;
+        p.ebase = ebase;
+        const double t = std::floor(sp.p_inter * 4294967296.0);
+        p.thr_p = t <= 0.0 ? 0 : (t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t);
+        p.m = sp.m;
+        p.P = sp.P;
+        p.CT = choose_ct(sp.P);
+        p.T1 = (uint32_t)((Lmax * sp.m + p.CT - 1) / p.CT);
+        p.H0 = H0;
+        p.seg0 = seg0;
+        p.key0 = (uint32_t)sp.seed;
+        p.key1 = (uint32_t)(sp.seed >> 32);
+        p.tag1 = TAG_PBA1 | (sp.graph_id << 8);
+        p.tag2 = TAG_PBA2 | (sp.graph_id << 8);
+        ebase += sp.n * sp.m;
+        H0 += (uint64_t)sp.P * p.T1 * sp.P;
+        seg0 += sp.P;
+        if (count > 1)
+            for (uint32_t q = 0; q < sp.P; ++q) seg_graph.push_back(g);
+    }
+    Graphs G;
+    memset(&G, 0, sizeof(G));
+    G.one = table[0];
+    bool uploaded = false;
+    if (count > 1) {
+        PGraph *d_table = reinterpret_cast<PGraph *>(ws + pl.off_table);
+        uint32_t *d_seg = reinterpret_cast<uint32_t *>(ws + pl.off_seg);
+        if (hipMemcpyAsync(d_table, table.data(), table.size() * sizeof(PGraph), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(d_seg, seg_graph.data(), seg_graph.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+            return check_launch("pba: table upload");
+        G.table = d_table;
+        G.seg_graph = d_seg;
+        uploaded = true;
+    }
     Factions fac{nullptr, nullptr, nullptr, nullptr};
     if (faction_off) {
         uint32_t *d_foff = reinterpret_cast<uint32_t *>(ws + pl.off_foff);
@@ -553,52 +714,88 @@ extern "C" int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p
             hipMemcpyAsync(d_uoff, uoff.data(), uoff.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
             (!umem.empty() && hipMemcpyAsync(d_umem, umem.data(), umem.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess))
             return check_launch("pba_generate: faction upload");
-        // The host vectors die at return: wait for the copies.
-        if (hipStreamSynchronize(s) != hipSuccess) return check_launch("pba_generate: faction upload");
         fac = Factions{d_foff, d_fmem, d_uoff, d_umem};
+        uploaded = true;
     }
-    const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
+    // The host tables die at return: wait for their copies.
+    if (uploaded && hipStreamSynchronize(s) != hipSuccess) return check_launch("pba: table upload");
+
     const int cus = device_cu_count();
     const int res_grid = cus * 8;
+    const uint32_t S = pl.S;
 
     // Phase 1.
-    { ProfScope _ps("pba_tile_table", s); pba_phase1_bases<<<(P + 1 + 255) / 256, 256, 0, s>>>(n, P, m, base1); }
-    Draw1Args d1{n, P, m, key0, key1, TAG_PBA1 | (graph_id << 8), 0, fac, lab};
-    {
-        double t = std::floor(p_inter * 4294967296.0);
-        d1.thr_p = t <= 0.0 ? 0 : (t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t);
-    }
-    // Grid-stride launches: a dispatch's work-item count per dimension must
-    // stay below 2^32.
-    const uint64_t per_part = (pl.Lmax * m + kDrawThreads - 1) / kDrawThreads;
-    dim3 g1((unsigned)std::min<uint64_t>(per_part, std::max<uint64_t>(1, (uint64_t)cus * 64 / P + 1)), P);
-    { ProfScope _ps("pba_draw1", s); pba_draw1<<<g1, kDrawThreads, 0, s>>>(d1); }
-    { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<1, 64, 0, s>>>(base1, P, pl.xstride, xpre, xtot, queues); }
-    { ProfScope _ps("pba_resolve", s); pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{lab, base1, xpre, xtot, queues, err, P, pl.xstride}); }
+    { ProfScope _ps("pba_tile_table", s); pba_bases1<<<(S + 1 + 255) / 256, 256, 0, s>>>(G, S, pl.E, base1); }
+    uint64_t max_slots = 0;
+    for (uint32_t g = 0; g < count; ++g)
+        max_slots = std::max<uint64_t>(max_slots, ((gs[g].n + gs[g].P - 1) / gs[g].P) * gs[g].m);
+    // Workgroups per segment: enough to fill the chip, and a dispatch's
+    // work-item count stays far below 2^32.
+    const uint64_t want = (max_slots + kDrawThreads - 1) / kDrawThreads;
+    const uint32_t chunks = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>(want, std::max<uint64_t>(1, (uint64_t)cus * 64 / S + 1)));
+    Draw1Args d1{G, base1, chunks, fac, lab};
+    { ProfScope _ps("pba_draw1", s); pba_draw1<<<S * chunks, kDrawThreads, 0, s>>>(d1); }
+    { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<kXcd, 1024, 0, s>>>(base1, S, pl.xstride, xpre, xtot, queues); }
+    { ProfScope _ps("pba_resolve", s); pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{lab, base1, xpre, xtot, queues, err, S, pl.xstride}); }
 
     // Count exchange.
-    dim3 gc(pl.T1, P);
-    { ProfScope _ps("pba_count", s); pba_count<<<gc, 256, P * 4, s>>>(CountArgs{lab, base1, H, P, pl.T1, pl.CT}); }
-    dim3 gs((unsigned)pl.groups, (P + 255) / 256);
-    { ProfScope _ps("pba_scan", s); pba_scan_partial<<<gs, 256, 0, s>>>(H, pl.R, P, part); }
-    { ProfScope _ps("pba_scan", s); pba_scan_groups<<<(P + 255) / 256, 256, 0, s>>>(part, pl.groups, P, D, err); }
-    { ProfScope _ps("pba_scan", s); pba_scan_apply<<<gs, 256, 0, s>>>(H, pl.R, P, part); }
-    { ProfScope _ps("pba_scan", s); pba_list_bases<<<1, 1024, 0, s>>>(D, P, sbase); }
+    { ProfScope _ps("pba_count", s); pba_count<<<S * pl.T1max, 256, pl.Pmax * 4, s>>>(CountArgs{G, lab, base1, H, pl.T1max}); }
+    if (pl.grouped) {
+        const uint32_t P = gs[0].P;
+        const uint64_t R = (uint64_t)P * table[0].T1;
+        dim3 gsc((unsigned)pl.groups, (P + 255) / 256);
+        { ProfScope _ps("pba_scan", s); pba_scan_partial<<<gsc, 256, 0, s>>>(H, R, P, part); }
+        { ProfScope _ps("pba_scan", s); pba_scan_groups<<<(P + 255) / 256, 256, 0, s>>>(part, pl.groups, P, D, err); }
+        { ProfScope _ps("pba_scan", s); pba_scan_apply<<<gsc, 256, 0, s>>>(H, R, P, part); }
+    } else {
+        { ProfScope _ps("pba_scan", s); pba_scan_columns<<<(S + 255) / 256, 256, 0, s>>>(G, S, H, D, err); }
+    }
+    { ProfScope _ps("pba_scan", s); pba_list_bases<<<1, 1024, 0, s>>>(D, S, sbase); }
 
     // Phase 2.
-    Draw2Args d2{n, P, pl.E, key0, key1, TAG_PBA2 | (graph_id << 8), sbase, sel};
+    Draw2Args d2{G, S, pl.E, sbase, sel};
     { ProfScope _ps("pba_draw2", s); pba_draw2<<<(unsigned)std::min<uint64_t>((pl.E + kDrawThreads - 1) / kDrawThreads, (uint64_t)cus * 64), kDrawThreads, 0, s>>>(d2); }
-    { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<1, 64, 0, s>>>(sbase, P, pl.xstride, xpre, xtot, queues + kXcd); }
-    { ProfScope _ps("pba_resolve", s); pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{sel, sbase, xpre, xtot, queues + kXcd, err, P, pl.xstride}); }
+    { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<kXcd, 1024, 0, s>>>(sbase, S, pl.xstride, xpre, xtot, queues + kXcd); }
+    { ProfScope _ps("pba_resolve", s); pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{sel, sbase, xpre, xtot, queues + kXcd, err, S, pl.xstride}); }
 
     // Substitution.
-    uint32_t lbits = 0;
-    while ((1u << lbits) < P) ++lbits;
-    SubArgs sa{n, P, m, pl.T1, pl.CT, lbits, lab, base1, H, sbase, sel, src, dst};
-    dim3 gsub(pl.T1, P);
-    if (id_bytes == 4)
-        { ProfScope _ps("pba_substitute", s); pba_substitute<int32_t><<<gsub, kSubThreads, lds_sub, s>>>(sa); }
-    else
-        { ProfScope _ps("pba_substitute", s); pba_substitute<int64_t><<<gsub, kSubThreads, lds_sub, s>>>(sa); }
-    return check_launch("pba_generate");
+    SubArgs sa{G, lab, base1, H, sbase, sel, src, dst, pl.T1max, pl.Pmax};
+    const bool match = pl.Pmax <= kMatchParts;
+    const size_t lds = (size_t)4 * pl.Pmax * 4 + (match ? (size_t)4 * pl.Pmax * 8 : 0);
+    const unsigned gsub = S * pl.T1max;
+    {
+        ProfScope _ps("pba_substitute", s);
+        if (id_bytes == 4) {
+            if (match)
+                pba_substitute<int32_t, true><<<gsub, kSubThreads, lds, s>>>(sa);
+            else
+                pba_substitute<int32_t, false><<<gsub, kSubThreads, lds, s>>>(sa);
+        } else {
+            if (match)
+                pba_substitute<int64_t, true><<<gsub, kSubThreads, lds, s>>>(sa);
+            else
+                pba_substitute<int64_t, false><<<gsub, kSubThreads, lds, s>>>(sa);
+        }
+    }
+    return check_launch(who);
+}
+
+}  // namespace sfg
+
+using namespace sfg;
+
+extern "C" size_t pba_workspace_bytes(uint64_t n, uint32_t m, uint32_t num_parts, uint64_t num_faction_members) {
+    if (num_parts == 0 || m == 0 || n == 0) return 0;
+    PbaGraphSpec g{n, m, num_parts, 0.0, 0, 0, 0};
+    return plan_batch(&g, 1, num_faction_members).total;
+}
+
+extern "C" int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p_inter, const uint32_t *faction_off,
+                            const uint32_t *faction_members, uint64_t seed, uint32_t graph_id, int id_bytes, void *src,
+                            void *dst, void *workspace, size_t workspace_bytes, void *stream) {
+    if (id_bytes != 4 && id_bytes != 8) return fail(SFG_EINVAL, "pba_generate: id_bytes must be 4 or 8");
+    PbaGraphSpec g{n, m, num_parts, p_inter, seed, graph_id, 0};
+    return pba_run_batch(&g, 1, faction_off, faction_members, id_bytes, src, dst, workspace, workspace_bytes,
+                         as_stream(stream));
 }

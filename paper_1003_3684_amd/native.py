@@ -43,7 +43,32 @@ SIGNATURES = {
     "pba_generate": (_i32, [_u64, _u32, _u32, _dbl, _vp, _vp, _u64, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "edges_to_csr_workspace_bytes": (_sz, [_u64, _u64, _i32, _u32]),
     "edges_to_csr": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "graph_stats_workspace_bytes": (_sz, [_u64, _u64, _i32]),
+    "graph_stats": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _u64, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ensemble_workspace_bytes": (_sz, [_vp, _u32, _u64]),
+    "ensemble_generate": (_i32, [_vp, _u32, _u32, _u64, _u64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mlp_param_count": (_sz, [_vp]),
+    "mlp_workspace_bytes": (_sz, [_vp, _u32]),
+    "mlp_forward": (_i32, [_vp, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mlp_backward": (_i32, [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "mlp_mse_grad": (_i32, [_u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "adam_step": (_i32, [_u64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float, _u32, _vp]),
 }
+
+
+class MlpShape(C.Structure):
+    """sfg_mlp_shape of include/sfgen.h."""
+    _fields_ = [("d_in", C.c_uint32), ("width", C.c_uint32), ("d_out", C.c_uint32), ("hidden", C.c_uint32)]
+
+
+class GraphDesc(C.Structure):
+    """sfg_graph_desc of include/sfgen.h."""
+    _fields_ = [("kind", C.c_int32), ("graph_id", C.c_uint32), ("seed", C.c_uint64), ("n", C.c_uint64),
+                ("m", C.c_uint32), ("num_parts", C.c_uint32), ("p_inter", C.c_double), ("n0", C.c_uint32),
+                ("k", C.c_uint32), ("num_edges", C.c_uint64), ("initiator", C.c_float * 16)]
+
+
+GRAPH_PBA, GRAPH_KRON = 0, 1
 
 
 def load(path: str = LIB_PATH):
@@ -196,3 +221,116 @@ def edges_to_csr(n, src, dst, *, flags=0, want_hist=True, want_dups=True, row_pt
     _check(lib.edges_to_csr(n, E, _ptr(src), _ptr(dst), id_bytes, flags, _ptr(row_ptr), _ptr(col), _ptr(hist),
                             _ptr(dups), _ptr(ws), ws.numel(), _stream(stream)))
     return row_ptr, col, hist, dups
+
+
+# ----------------------------------------------------------------------------- statistics
+def graph_stats_workspace_bytes(n, num_edges, id_bytes):
+    return int(load().graph_stats_workspace_bytes(n, num_edges, id_bytes))
+
+
+def graph_stats(n, src, dst, *, num_samples=10_000, seed=0, graph_id=0, ws=None, out=None, stream=None):
+    """(hist32, gamma, closed) device tensors for one edge list."""
+    _require_cuda()
+    lib = load()
+    id_bytes = src.element_size()
+    E = src.numel()
+    if out is None:
+        out = (torch.empty(32, dtype=torch.int64, device=src.device), torch.empty(1, dtype=torch.float64, device=src.device),
+               torch.empty(1, dtype=torch.int64, device=src.device))
+    hist, gamma, closed = out
+    if ws is None:
+        ws = workspace(graph_stats_workspace_bytes(n, E, id_bytes), src.device)
+    _check(lib.graph_stats(n, E, _ptr(src), _ptr(dst), id_bytes, num_samples, seed, graph_id, _ptr(hist), _ptr(gamma),
+                           _ptr(closed), _ptr(ws), ws.numel(), _stream(stream)))
+    return hist, gamma, closed
+
+
+# ----------------------------------------------------------------------------- ensemble
+def graph_descs(rows):
+    """ctypes array of GraphDesc from dicts (kind 'pba' or 'kron')."""
+    arr = (GraphDesc * len(rows))()
+    for d, r in zip(arr, rows):
+        d.graph_id = r["graph_id"]
+        d.seed = r["seed"]
+        if r["kind"] == "pba":
+            d.kind, d.n, d.m, d.num_parts, d.p_inter = GRAPH_PBA, r["n"], r["m"], r["num_parts"], r["p_inter"]
+        else:
+            import numpy as np
+            W = np.asarray(r["initiator"], np.float32).ravel()
+            d.kind, d.n0, d.k, d.num_edges = GRAPH_KRON, r["n0"], r["k"], r["num_edges"]
+            for i, x in enumerate(W):
+                d.initiator[i] = float(x)
+    return arr
+
+
+def ensemble_workspace_bytes(descs, max_batch_edges):
+    return int(load().ensemble_workspace_bytes(C.cast(descs, _vp), len(descs), max_batch_edges))
+
+
+def ensemble_generate(descs, *, num_samples=10_000, stat_seed=0, max_batch_edges=1 << 28, ws=None, out=None,
+                      stream=None):
+    """Batched ensemble: returns (hist [count,32], gamma [count], closed [count]) device tensors."""
+    _require_cuda()
+    lib = load()
+    count = len(descs)
+    if out is None:
+        out = (torch.empty((count, 32), dtype=torch.int64, device="cuda"),
+               torch.empty(count, dtype=torch.float64, device="cuda"),
+               torch.empty(count, dtype=torch.int64, device="cuda"))
+    hist, gamma, closed = out
+    if ws is None:
+        ws = workspace(ensemble_workspace_bytes(descs, max_batch_edges))
+    _check(lib.ensemble_generate(C.cast(descs, _vp), count, num_samples, stat_seed, max_batch_edges, _ptr(hist),
+                                 _ptr(gamma), _ptr(closed), _ptr(ws), ws.numel(), _stream(stream)))
+    return hist, gamma, closed
+
+
+# ----------------------------------------------------------------------------- MLP surrogate
+def mlp_shape(d_in, width=256, d_out=34, hidden=3):
+    return MlpShape(d_in, width, d_out, hidden)
+
+
+def mlp_param_count(shape):
+    return int(load().mlp_param_count(C.byref(shape)))
+
+
+def mlp_workspace_bytes(shape, batch):
+    return int(load().mlp_workspace_bytes(C.byref(shape), batch))
+
+
+def mlp_forward(shape, params, x, ws, y=None, stream=None):
+    lib = load()
+    B = x.shape[0]
+    if y is None:
+        y = torch.empty((B, shape.d_out), dtype=torch.float32, device=x.device)
+    _check(lib.mlp_forward(C.byref(shape), B, _ptr(params), _ptr(x), _ptr(y), _ptr(ws), ws.numel(), _stream(stream)))
+    return y
+
+
+def mlp_backward(shape, params, dy, ws, grad=None, dx=None, want_grad=True, want_dx=False, stream=None):
+    lib = load()
+    B = dy.shape[0]
+    if want_grad and grad is None:
+        grad = torch.empty(mlp_param_count(shape), dtype=torch.float32, device=dy.device)
+    if want_dx and dx is None:
+        dx = torch.empty((B, shape.d_in), dtype=torch.float32, device=dy.device)
+    _check(lib.mlp_backward(C.byref(shape), B, _ptr(params), _ptr(dy), _ptr(grad if want_grad else None),
+                            _ptr(dx if want_dx else None), _ptr(ws), ws.numel(), _stream(stream)))
+    return grad, dx
+
+
+def mlp_mse_grad(y, target, ws, mask=None, col_weight=None, dy=None, loss=None, stream=None):
+    lib = load()
+    B, D = y.shape
+    if dy is None:
+        dy = torch.empty_like(y)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=y.device)
+    _check(lib.mlp_mse_grad(B, D, _ptr(y), _ptr(target), _ptr(mask), _ptr(col_weight), _ptr(dy), _ptr(loss), _ptr(ws),
+                            ws.numel(), _stream(stream)))
+    return dy, loss
+
+
+def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(load().adam_step(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), lr, beta1, beta2, eps, step,
+                            _stream(stream)))

@@ -1,0 +1,204 @@
+"""MLP surrogate: generator parameters -> graph statistics, trained on the
+ensembles the generators produce and inverted to choose Kronecker parameters
+for a target degree exponent.  The real generator stays the judge: a proposal
+is accepted only when the generated graph's measured exponent is within the
+tolerance, and the generator-only search takes over otherwise.
+
+Everything numerical runs in the library's kernels: ensemble_generate makes
+the training data, mlp_forward / mlp_backward / mlp_mse_grad / adam_step train
+the network and give input gradients for the inversion.  This module only
+encodes features, schedules the steps and keeps score.
+"""
+import math
+
+import numpy as np
+import torch
+
+from . import native as sfg
+
+D_IN = 10      # [is_pba, is_kron, log2(n)/20, m/8, 2p, W00, W01, W10, W11, k/20]
+D_OUT = 34     # 32 log-frequency bins, gamma, closed-wedge fraction
+GAMMA_COL = 32
+
+
+def features(rows):
+    X = np.zeros((len(rows), D_IN), np.float32)
+    for i, r in enumerate(rows):
+        if r["kind"] == "pba":
+            X[i, 0] = 1
+            X[i, 2] = math.log2(r["n"]) / 20
+            X[i, 3] = r["m"] / 8
+            X[i, 4] = 2 * r["p_inter"]
+        else:
+            X[i, 1] = 1
+            X[i, 2] = r["k"] / 20
+            X[i, 5:9] = np.asarray(r["initiator"], np.float32).ravel()[:4]
+            X[i, 9] = r["k"] / 20
+    return X
+
+
+def targets(rows, hist, gamma, closed, samples):
+    """(Y, mask): log(1e-6 + bin share), gamma, closed share; missing values masked."""
+    n = np.array([r["n"] if r["kind"] == "pba" else r["n0"] ** r["k"] for r in rows], np.float64)
+    Y = np.zeros((len(rows), D_OUT), np.float32)
+    M = np.ones((len(rows), D_OUT), np.float32)
+    Y[:, :32] = np.log(1e-6 + hist / n[:, None])
+    g = np.asarray(gamma, np.float64)
+    ok = np.isfinite(g)
+    Y[:, GAMMA_COL] = np.where(ok, g, 0)
+    M[:, GAMMA_COL] = ok
+    c = np.asarray(closed, np.float64)
+    Y[:, 33] = np.where(c >= 0, c / max(samples, 1), 0)
+    M[:, 33] = c >= 0
+    return Y, M
+
+
+def generate_dataset(rows, samples=10_000, stat_seed=0, max_batch_edges=1 << 28, ws=None):
+    """Statistics of every graph in `rows` via the batched ensemble."""
+    descs = sfg.graph_descs(rows)
+    hist, gamma, closed = sfg.ensemble_generate(descs, num_samples=samples, stat_seed=stat_seed,
+                                                max_batch_edges=max_batch_edges, ws=ws)
+    torch.cuda.synchronize()
+    return targets(rows, hist.cpu().numpy().astype(np.float64), gamma.cpu().numpy(), closed.cpu().numpy(), samples)
+
+
+class Surrogate:
+    def __init__(self, width=256, hidden=3, seed=0, batch=4096):
+        self.shape = sfg.mlp_shape(D_IN, width, D_OUT, hidden)
+        rng = np.random.default_rng(seed)
+        P = sfg.mlp_param_count(self.shape)
+        p = np.zeros(P, np.float32)
+        off = 0
+        dims = [D_IN] + [width] * hidden + [D_OUT]
+        for i in range(len(dims) - 1):
+            n_in, n_out = dims[i], dims[i + 1]
+            p[off:off + n_in * n_out] = rng.normal(0, math.sqrt(2.0 / n_in), size=n_in * n_out)
+            off += n_in * n_out + n_out
+        self.params = torch.tensor(p).cuda()
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self.batch = batch
+        self.ws = sfg.workspace(sfg.mlp_workspace_bytes(self.shape, batch))
+        self.lws = sfg.workspace(4 * batch)
+        self.mu = np.zeros(D_OUT, np.float32)
+        self.sd = np.ones(D_OUT, np.float32)
+
+    def fit(self, X, Y, M, epochs=30, lr=1e-3, seed=0, col_weight=None):
+        """Adam on standardized targets; returns the per-epoch mean loss."""
+        rng = np.random.default_rng(seed)
+        Mb = M.astype(bool)
+        for j in range(D_OUT):
+            col = Y[Mb[:, j], j]
+            if col.size:
+                self.mu[j] = col.mean()
+                self.sd[j] = max(col.std(), 1e-3)
+        Ys = (Y - self.mu) / self.sd * M
+        cw = torch.tensor(np.ones(D_OUT, np.float32) if col_weight is None else col_weight).cuda()
+        Xg, Yg, Mg = (torch.tensor(a).cuda() for a in (X, Ys.astype(np.float32), M))
+        history = []
+        N = X.shape[0]
+        for ep in range(epochs):
+            order = torch.tensor(rng.permutation(N)).cuda()
+            tot, nb = 0.0, 0
+            lr_ep = lr * 0.5 * (1 + math.cos(math.pi * ep / max(epochs, 1)))
+            for b0 in range(0, N - self.batch + 1, self.batch):
+                idx = order[b0:b0 + self.batch]
+                xb, yb, mb = Xg[idx].contiguous(), Yg[idx].contiguous(), Mg[idx].contiguous()
+                y = sfg.mlp_forward(self.shape, self.params, xb, self.ws)
+                dy, loss = sfg.mlp_mse_grad(y, yb, self.lws, mask=mb, col_weight=cw)
+                grad, _ = sfg.mlp_backward(self.shape, self.params, dy, self.ws)
+                self.step += 1
+                sfg.adam_step(self.params, grad, self.m, self.v, self.step, lr=lr_ep)
+                tot += float(loss.item())
+                nb += 1
+            history.append(tot / max(nb, 1))
+        return history
+
+    def predict(self, X):
+        out = []
+        for b0 in range(0, X.shape[0], self.batch):
+            xb = torch.tensor(X[b0:b0 + self.batch]).cuda()
+            y = sfg.mlp_forward(self.shape, self.params, xb, self.ws)
+            out.append(y.cpu().numpy() * self.sd + self.mu)
+        return np.concatenate(out, 0)
+
+    def gamma_and_grad(self, X):
+        """Predicted gamma and d gamma / dX for a batch of feature rows."""
+        xb = torch.tensor(X).cuda()
+        y = sfg.mlp_forward(self.shape, self.params, xb, self.ws)
+        dy = torch.zeros_like(y)
+        dy[:, GAMMA_COL] = 1.0
+        _, dx = sfg.mlp_backward(self.shape, self.params, dy, self.ws, want_grad=False, want_dx=True)
+        g = y[:, GAMMA_COL].cpu().numpy() * self.sd[GAMMA_COL] + self.mu[GAMMA_COL]
+        return g, dx.cpu().numpy() * self.sd[GAMMA_COL]
+
+
+# ----------------------------------------------------------------------------- inversion
+def kron_row(a, b, k, seed, graph_id=0):
+    """The 2x2 row-stochastic initiator family [[a, 1-a], [b, 1-b]]."""
+    W = np.array([[a, 1 - a], [b, 1 - b]], np.float32)
+    return dict(kind="kron", graph_id=graph_id, n0=2, initiator=W, k=k, num_edges=16 << k, seed=seed)
+
+
+class Judge:
+    """Runs the real generator and measures the exponent; counts the calls."""
+
+    def __init__(self, k=14, seeds=(101,), samples=2000):
+        self.k, self.seeds, self.samples, self.calls = k, seeds, samples, 0
+        E = 16 << k
+        self.ws = sfg.workspace(sfg.graph_stats_workspace_bytes(2 ** k, E, 4))
+
+    def gamma(self, a, b):
+        vals = []
+        for s in self.seeds:
+            r = kron_row(a, b, self.k, s)
+            src, dst = sfg.kron_generate(2, r["initiator"], self.k, r["num_edges"], seed=s)
+            _, g, _ = sfg.graph_stats(2 ** self.k, src, dst, num_samples=self.samples, seed=s, ws=self.ws)
+            self.calls += 1
+            vals.append(float(g.item()))
+        return float(np.mean(vals))
+
+
+def invert(model, target, k, restarts=16, iters=60, lr=0.05, seed=0, bounds=(0.03, 0.97)):
+    """Projected gradient descent on (a, b) so that the predicted exponent
+    equals `target`; returns the candidates ordered by predicted error."""
+    rng = np.random.default_rng(seed)
+    ab = rng.uniform(bounds[0], bounds[1], size=(restarts, 2))
+    for _ in range(iters):
+        X = features([kron_row(a, b, k, 0) for a, b in ab])
+        g, dX = model.gamma_and_grad(X)
+        err = g - target
+        # x5..x8 = (a, 1-a, b, 1-b): chain rule to (a, b)
+        da = dX[:, 5] - dX[:, 6]
+        db = dX[:, 7] - dX[:, 8]
+        step = np.stack([err * da, err * db], 1)
+        ab = np.clip(ab - lr * step, *bounds)
+    X = features([kron_row(a, b, k, 0) for a, b in ab])
+    g, _ = model.gamma_and_grad(X)
+    order = np.argsort(np.abs(g - target))
+    return ab[order], g[order]
+
+
+def search_generator_only(judge, target, tol, budget=40, seed=0):
+    """Baseline without the surrogate: random search over the (a, b) family,
+    one generator run per candidate; returns (accepted, calls)."""
+    rng = np.random.default_rng(seed)
+    calls0 = judge.calls
+    while judge.calls - calls0 < budget:
+        a, b = rng.uniform(0.03, 0.97, size=2)
+        if abs(judge.gamma(a, b) - target) <= tol:
+            return True, judge.calls - calls0
+    return False, judge.calls - calls0
+
+
+def search_with_surrogate(model, judge, target, tol, budget=40, seed=0):
+    """Surrogate proposals judged by the generator, best first; falls back to
+    the generator-only search for the remaining budget."""
+    calls0 = judge.calls
+    cands, _ = invert(model, target, judge.k, seed=seed)
+    for a, b in cands[:4]:
+        if abs(judge.gamma(a, b) - target) <= tol:
+            return True, judge.calls - calls0
+    ok, more = search_generator_only(judge, target, tol, budget - (judge.calls - calls0), seed)
+    return ok, judge.calls - calls0

@@ -88,3 +88,22 @@ def ensemble_table(count=4096, seed=17):
             k = int(rng.integers(10, 21))
             rows.append(dict(kind="kron", graph_id=g, n0=2, initiator=W, k=k, num_edges=16 << k, seed=seed))
     return rows
+
+
+def small_ensemble_table(count=48, seed=23, log2_n=(10, 14), k_range=(10, 14), parts=8):
+    """The ensemble recipe at test sizes: PBA with n log-uniform in
+    [2^log2_n[0], 2^log2_n[1]] and `parts` partitions; Kronecker with k in
+    k_range and 16 * 2^k edges."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    for g in range(count):
+        if g % 2 == 0:
+            n = int(np.floor(2.0 ** rng.uniform(*log2_n)))
+            rows.append(dict(kind="pba", graph_id=g, n=n, m=int(rng.integers(2, 9)),
+                             p_inter=float(rng.uniform(0.0, 0.5)), num_parts=parts, seed=seed))
+        else:
+            W = rng.uniform(0.02, 0.7, size=(2, 2)).astype(np.float32)
+            W = (W / W.sum(axis=1, keepdims=True)).astype(np.float32)
+            k = int(rng.integers(k_range[0], k_range[1] + 1))
+            rows.append(dict(kind="kron", graph_id=g, n0=2, initiator=W, k=k, num_edges=16 << k, seed=seed))
+    return rows

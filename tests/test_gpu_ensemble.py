@@ -1,0 +1,86 @@
+"""The batched ensemble equals the plain per-graph calls member by member
+(edges through the same kernels and streams, statistics bit for bit), and a
+sample of members equals the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1003_3684_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+STAT_SEED = 99
+
+
+def _plain(sfg, rows, samples):
+    import torch
+    out = []
+    for r in rows:
+        if r["kind"] == "pba":
+            src, dst = sfg.pba_generate(r["n"], r["m"], r["num_parts"], r["p_inter"], seed=r["seed"],
+                                        graph_id=r["graph_id"])
+            n = r["n"]
+        else:
+            src, dst = sfg.kron_generate(r["n0"], r["initiator"], r["k"], r["num_edges"], seed=r["seed"],
+                                         graph_id=r["graph_id"])
+            n = r["n0"] ** r["k"]
+        h, g, c = sfg.graph_stats(n, src, dst, num_samples=samples, seed=STAT_SEED, graph_id=r["graph_id"])
+        out.append((h.cpu().numpy(), float(g.item()), int(c.item())))
+    torch.cuda.synchronize()
+    return out
+
+
+def _same_gamma(a, b):
+    return (math.isnan(a) and math.isnan(b)) or a == b
+
+
+@pytest.mark.parametrize("max_batch_edges", [1 << 16, 1 << 30])
+def test_ensemble_equals_plain(sfg, max_batch_edges):
+    import torch
+    rows = wl.small_ensemble_table(48)
+    descs = sfg.graph_descs(rows)
+    hist, gamma, closed = sfg.ensemble_generate(descs, num_samples=2000, stat_seed=STAT_SEED,
+                                                max_batch_edges=max_batch_edges)
+    torch.cuda.synchronize()
+    assert sfg.device_error() == 0
+    plain = _plain(sfg, rows, 2000)
+    hist, gamma, closed = hist.cpu().numpy(), gamma.cpu().numpy(), closed.cpu().numpy()
+    for i, (h, g, c) in enumerate(plain):
+        np.testing.assert_array_equal(hist[i], h, err_msg=f"member {i}")
+        assert closed[i] == c, (i, closed[i], c)
+        assert _same_gamma(float(gamma[i]), g), (i, gamma[i], g)
+
+
+def test_ensemble_members_match_oracle(sfg, orc):
+    import torch
+    rows = wl.small_ensemble_table(12, seed=5)
+    descs = sfg.graph_descs(rows)
+    hist, gamma, closed = sfg.ensemble_generate(descs, num_samples=3000, stat_seed=STAT_SEED, max_batch_edges=1 << 20)
+    torch.cuda.synchronize()
+    hist, gamma, closed = hist.cpu().numpy(), gamma.cpu().numpy(), closed.cpu().numpy()
+    for i, r in enumerate(rows):
+        if r["kind"] == "pba":
+            src, dst = orc.pba_generate(r["n"], r["m"], r["num_parts"], r["p_inter"], r["seed"], r["graph_id"])
+            n = r["n"]
+        else:
+            src, dst = orc.kron_sample(r["n0"], r["initiator"], r["k"], r["num_edges"], r["seed"], r["graph_id"])
+            n = r["n0"] ** r["k"]
+        oh, og, oc = orc.graph_stats(n, src, dst, 3000, STAT_SEED, r["graph_id"])
+        np.testing.assert_array_equal(hist[i].astype(np.uint64), oh)
+        assert closed[i] == oc
+        if math.isnan(og):
+            assert math.isnan(gamma[i])
+        else:
+            assert abs(gamma[i] - og) <= 1e-9 * abs(og)
+
+
+def test_ensemble_workspace_and_errors(sfg):
+    rows = wl.small_ensemble_table(6)
+    descs = sfg.graph_descs(rows)
+    need_small = sfg.ensemble_workspace_bytes(descs, 1 << 12)
+    need_big = sfg.ensemble_workspace_bytes(descs, 1 << 30)
+    assert 0 < need_small <= need_big
+    ws = sfg.workspace(need_small - 256)
+    with pytest.raises(sfg.SfgenError):
+        sfg.ensemble_generate(descs, max_batch_edges=1 << 12, ws=ws)

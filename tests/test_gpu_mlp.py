@@ -1,0 +1,105 @@
+"""GPU MLP kernels against the float64 oracle with the same bfloat16 rounding
+points.  Tolerances: float32 accumulation of K <= 256 bf16 products differs
+from float64 by ~1e-6 relative, and a bf16 rounding tie can flip one input
+by 2^-8; outputs are compared at 1e-3 and gradients at 1e-2 of their scale."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(sfg, shape_t, batch, seed):
+    import torch
+    rng = np.random.default_rng(seed)
+    shape = sfg.mlp_shape(*shape_t)
+    P = sfg.mlp_param_count(shape)
+    _, total = omlp.layers(*shape_t)
+    assert P == total
+    params = rng.normal(0, 1.0 / np.sqrt(shape_t[1]), size=P).astype(np.float32)
+    x = rng.normal(size=(batch, shape_t[0])).astype(np.float32)
+    t = rng.normal(size=(batch, shape_t[2])).astype(np.float32)
+    g = dict(params=torch.tensor(params).cuda(), x=torch.tensor(x).cuda(), t=torch.tensor(t).cuda(),
+             ws=sfg.workspace(sfg.mlp_workspace_bytes(shape, batch)))
+    return shape, params, x, t, g
+
+
+def _close(a, b, rel):
+    scale = np.max(np.abs(b)) + 1e-30
+    np.testing.assert_allclose(a, b, rtol=rel, atol=rel * scale)
+
+
+@pytest.mark.parametrize("shape_t,batch", [((10, 256, 34, 3), 1000), ((10, 256, 34, 3), 1),
+                                           ((5, 70, 7, 2), 63), ((3, 40, 130, 1), 257)])
+def test_mlp_forward_backward(sfg, shape_t, batch):
+    import torch
+    shape, params, x, t, g = _setup(sfg, shape_t, batch, 7 + batch)
+    y = sfg.mlp_forward(shape, g["params"], g["x"], g["ws"])
+    torch.cuda.synchronize()
+    yo, cache = omlp.forward(shape_t, params.astype(np.float64), x.astype(np.float64))
+    _close(y.cpu().numpy(), yo, 1e-3)
+    # loss gradient on the GPU against the oracle's, then backward from the same dy
+    lws = sfg.workspace(4 * batch)
+    dy, loss = sfg.mlp_mse_grad(y, g["t"], lws)
+    dyo, losso = omlp.mse_grad(y.cpu().numpy().astype(np.float64), t.astype(np.float64))
+    _close(dy.cpu().numpy(), dyo, 1e-5)
+    assert abs(float(loss.item()) - losso) <= 1e-5 * abs(losso)
+    grad, dx = sfg.mlp_backward(shape, g["params"], dy, g["ws"], want_dx=True)
+    torch.cuda.synchronize()
+    go, dxo = omlp.backward(shape_t, params.astype(np.float64), cache, dy.cpu().numpy().astype(np.float64))
+    _close(grad.cpu().numpy(), go, 1e-2)
+    _close(dx.cpu().numpy(), dxo, 1e-2)
+
+
+def test_mse_mask_and_weights(sfg):
+    import torch
+    rng = np.random.default_rng(5)
+    y = rng.normal(size=(50, 9)).astype(np.float32)
+    t = rng.normal(size=(50, 9)).astype(np.float32)
+    mask = (rng.uniform(size=y.shape) > 0.3).astype(np.float32)
+    w = rng.uniform(0.1, 3, size=9).astype(np.float32)
+    dy, loss = sfg.mlp_mse_grad(torch.tensor(y).cuda(), torch.tensor(t).cuda(), sfg.workspace(200),
+                                mask=torch.tensor(mask).cuda(), col_weight=torch.tensor(w).cuda())
+    dyo, losso = omlp.mse_grad(y.astype(np.float64), t.astype(np.float64), mask, w)
+    _close(dy.cpu().numpy(), dyo, 1e-6)
+    assert abs(float(loss.item()) - losso) <= 1e-5 * losso
+
+
+def test_adam_matches_oracle(sfg):
+    import torch
+    rng = np.random.default_rng(6)
+    p = rng.normal(size=1000).astype(np.float32)
+    po, mo, vo = p.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    pg, m, v = torch.tensor(p).cuda(), torch.zeros(1000).cuda(), torch.zeros(1000).cuda()
+    for step in range(1, 6):
+        gr = rng.normal(size=1000).astype(np.float32)
+        sfg.adam_step(pg, torch.tensor(gr).cuda(), m, v, step, lr=1e-2)
+        po, mo, vo = omlp.adam(po, gr.astype(np.float64), mo, vo, step, lr=1e-2)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(pg.cpu().numpy(), po, rtol=1e-5, atol=1e-6)
+
+
+def test_training_reduces_loss(sfg):
+    """A few hundred Adam steps on a smooth synthetic regression."""
+    import torch
+    shape_t = (4, 64, 3, 2)
+    shape = sfg.mlp_shape(*shape_t)
+    rng = np.random.default_rng(8)
+    B = 512
+    x = rng.uniform(-1, 1, size=(B, 4)).astype(np.float32)
+    t = np.stack([np.sin(2 * x[:, 0]), x[:, 1] * x[:, 2], np.cos(x[:, 3])], 1).astype(np.float32)
+    P = sfg.mlp_param_count(shape)
+    params = torch.tensor(rng.normal(0, 0.3, size=P).astype(np.float32)).cuda()
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    xg, tg = torch.tensor(x).cuda(), torch.tensor(t).cuda()
+    ws, lws = sfg.workspace(sfg.mlp_workspace_bytes(shape, B)), sfg.workspace(4 * B)
+    losses = []
+    for step in range(1, 401):
+        y = sfg.mlp_forward(shape, params, xg, ws)
+        dy, loss = sfg.mlp_mse_grad(y, tg, lws)
+        grad, _ = sfg.mlp_backward(shape, params, dy, ws)
+        sfg.adam_step(params, grad, m, v, step, lr=3e-3)
+        if step in (1, 400):
+            losses.append(float(loss.item()))
+    assert losses[1] < 0.1 * losses[0], losses
