@@ -11,8 +11,8 @@ itself; every buffer is resident in HBM before the timed region starts.
 One JSON line is printed.  Besides the headline edges/s it carries the
 roofline of the dominant kernel (the radix-sort pass), the CPU oracle timed
 on a bounded sample of the same workload, the PBA workload (2^27 vertices,
-m = 5, 1,024 partitions) and the batched-versus-plain ensemble rate when the
-ensemble entry point is built.
+m = 5, 1,024 partitions) and the batched-versus-plain ensemble rate (4,096
+PBA and Kronecker graphs with their statistics).
 """
 import argparse
 import hashlib
@@ -178,7 +178,7 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_extras:
-        result["extras"] = {"pba": _bench_pba(sfg, wl, torch)}
+        result["extras"] = {"pba": _bench_pba(sfg, wl, torch), "ensemble": _bench_ensemble(sfg, wl, torch)}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_sample)
     print(json.dumps(result), flush=True)
@@ -220,6 +220,79 @@ def _bench_pba(sfg, wl, torch, reps=3):
     del src, dst, ws, rp, col
     torch.cuda.empty_cache()
     return out
+
+
+def _bench_ensemble(sfg, wl, torch, samples=10_000, stat_seed=5, max_batch_edges=1 << 30):
+    """Graphs/s of the batched ensemble entry point against the same 4,096
+    graphs made one by one (generator call, then the statistics call), with
+    the statistics compared member by member."""
+    import numpy as np
+    rows = wl.ensemble_table()
+    descs = sfg.graph_descs(rows)
+    count = len(rows)
+    edges = sum(r["n"] * r["m"] if r["kind"] == "pba" else r["num_edges"] for r in rows)
+    out = (torch.empty((count, 32), dtype=torch.int64, device="cuda"),
+           torch.empty(count, dtype=torch.float64, device="cuda"),
+           torch.empty(count, dtype=torch.int64, device="cuda"))
+    ws = sfg.workspace(sfg.ensemble_workspace_bytes(descs, max_batch_edges))
+    warm = sfg.graph_descs(rows[:64])
+    sfg.ensemble_generate(warm, num_samples=samples, stat_seed=stat_seed, max_batch_edges=max_batch_edges, ws=ws,
+                          out=tuple(t[:64] for t in out))
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    sfg.ensemble_generate(descs, num_samples=samples, stat_seed=stat_seed, max_batch_edges=max_batch_edges, ws=ws,
+                          out=out)
+    b.record()
+    torch.cuda.synchronize()
+    batched_s = a.elapsed_time(b) / 1e3
+    bh, bg, bc = (t.cpu().numpy() for t in out)
+    del ws
+    torch.cuda.empty_cache()
+
+    def nv(r):
+        return r["n"] if r["kind"] == "pba" else r["n0"] ** r["k"]
+
+    def ne(r):
+        return r["n"] * r["m"] if r["kind"] == "pba" else r["num_edges"]
+
+    emax = max(ne(r) for r in rows)
+    nmax = max(nv(r) for r in rows)
+    src = torch.empty(emax, dtype=torch.int32, device="cuda")
+    dst = torch.empty(emax, dtype=torch.int32, device="cuda")
+    pws = sfg.workspace(max(sfg.pba_workspace_bytes(r["n"], r["m"], r["num_parts"]) for r in rows if r["kind"] == "pba"))
+    sws = sfg.workspace(sfg.graph_stats_workspace_bytes(nmax, emax, 4))
+    ph = torch.empty((count, 32), dtype=torch.int64, device="cuda")
+    pg = torch.empty(count, dtype=torch.float64, device="cuda")
+    pc = torch.empty(count, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.record()
+    for i, r in enumerate(rows):
+        E = ne(r)
+        s_, d_ = src[:E], dst[:E]
+        if r["kind"] == "pba":
+            sfg.pba_generate(r["n"], r["m"], r["num_parts"], r["p_inter"], seed=r["seed"], graph_id=r["graph_id"],
+                             src=s_, dst=d_, ws=pws)
+        else:
+            sfg.kron_generate(r["n0"], r["initiator"], r["k"], E, seed=r["seed"], graph_id=r["graph_id"], src=s_,
+                              dst=d_)
+        sfg.graph_stats(nv(r), s_, d_, num_samples=samples, seed=stat_seed, graph_id=r["graph_id"], ws=sws,
+                        out=(ph[i], pg[i:i + 1], pc[i:i + 1]))
+    b.record()
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t0
+    plain_s = a.elapsed_time(b) / 1e3
+    same = bool(np.array_equal(bh, ph.cpu().numpy()) and np.array_equal(bc, pc.cpu().numpy())
+                and np.array_equal(bg, pg.cpu().numpy(), equal_nan=True))
+    del src, dst, pws, sws
+    torch.cuda.empty_cache()
+    return {"workload": f"ensemble_{count}_graphs_seed17", "graphs": count, "edges": edges,
+            "wedge_samples": samples, "max_batch_edges": max_batch_edges,
+            "batched_s": batched_s, "batched_graphs_per_s": count / batched_s,
+            "batched_edges_per_s": edges / batched_s,
+            "plain_s": plain_s, "plain_wall_s": plain_wall, "plain_graphs_per_s": count / plain_s,
+            "speedup": plain_s / batched_s, "stats_identical": same}
 
 
 if __name__ == "__main__":

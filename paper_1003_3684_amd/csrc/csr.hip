@@ -36,12 +36,15 @@ constexpr int kPassTile = kPassThreads * kPassItems;  // keys per onesweep tile
 constexpr int kPassWaves = kPassThreads / 64;
 constexpr int kRadix = 256;
 constexpr int kLookWindow = 4;  // predecessors read per look-back round trip
+constexpr int kXcdCount = 8;     // workgroup b runs on XCD b mod 8
+constexpr int kXcdRun = 16;      // consecutive tiles given to one XCD
 
 constexpr int kFinThreads = 256;
 constexpr int kFinItems = 16;
 constexpr int kFinTile = kFinThreads * kFinItems;
 
 constexpr int kScanChunk = 4096;  // vertices per chunk of the row fill scan
+constexpr int kPrepUnroll = 4;    // keys per thread in flight in the histogram pass
 
 constexpr uint64_t kNoRow = ~0ull;
 
@@ -109,10 +112,21 @@ __global__ __launch_bounds__(256) void csr_prepare(PrepArgs a) {
     for (int i = threadIdx.x; i < 8 * kRadix; i += 256) s_h[i] = 0;
     __syncthreads();
     const IdT *src = static_cast<const IdT *>(a.src), *dst = static_cast<const IdT *>(a.dst);
-    const uint64_t stride = (uint64_t)gridDim.x * 256;
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < a.N; i += stride) {
-        const KeyT k = entry_key<IdT, KeyT, SYM>(src, dst, a.E, i, a.wb);
-        for (int p = 0; p < a.passes; ++p) atomicAdd(&s_h[p * kRadix + (uint32_t)((k >> (8 * p)) & 255)], 1u);
+    // kPrepUnroll keys per thread are loaded before any is counted, so that
+    // enough loads are in flight to cover the memory latency.
+    const uint64_t stride = (uint64_t)gridDim.x * 256 * kPrepUnroll;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * 256 * kPrepUnroll + threadIdx.x; i0 < a.N; i0 += stride) {
+        KeyT k[kPrepUnroll];
+#pragma unroll
+        for (int u = 0; u < kPrepUnroll; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * 256;
+            k[u] = i < a.N ? entry_key<IdT, KeyT, SYM>(src, dst, a.E, i, a.wb) : (KeyT)0;
+        }
+#pragma unroll
+        for (int u = 0; u < kPrepUnroll; ++u) {
+            if (i0 + (uint64_t)u * 256 >= a.N) break;
+            for (int p = 0; p < a.passes; ++p) atomicAdd(&s_h[p * kRadix + (uint32_t)((k[u] >> (8 * p)) & 255)], 1u);
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < a.passes * kRadix; i += 256)
@@ -134,6 +148,23 @@ template <typename T> __global__ void fill_kernel(T *p, uint64_t n, T v) {
 }
 
 // --------------------------------------------------------------------------- onesweep pass
+// Tile of workgroup b out of `tiles`.  Workgroups are dispatched in id order,
+// round-robin over the XCDs, and neighbouring tiles write neighbouring pieces
+// of every digit run: the cache line at the seam of two pieces is written
+// half by each.  Handing kXcdRun consecutive tiles to one XCD puts both
+// halves of most seams in the same L2, which then writes the line back once
+// and whole instead of twice in part.  Within each XCD the tile numbers still
+// rise with the dispatch order (the tail that does not fill a group keeps
+// tile = b), which is what keeps the look-back free of deadlock: the smallest
+// unfinished tile is always dispatched and waits for nothing.
+__device__ __forceinline__ uint64_t tile_of_block(uint64_t b, uint64_t tiles) {
+    constexpr uint64_t G = (uint64_t)kXcdCount * kXcdRun;
+    const uint64_t g0 = b / G * G;
+    if (g0 + G > tiles) return b;
+    const uint64_t j = b - g0;
+    return g0 + (j % kXcdCount) * kXcdRun + j / kXcdCount;
+}
+
 struct PassArgs {
     uint64_t E, N;
     const void *src, *dst;  // first pass only
@@ -167,12 +198,9 @@ __global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
     const int tid = threadIdx.x;
     const uint32_t lane = tid & 63;
     const int w = tid >> 6;
-    // Tile = workgroup id.  Workgroups are dispatched in id order (round-robin
-    // over the XCDs), so every tile this one waits for in the look-back was
-    // dispatched earlier and is running or done: the smallest unfinished tile
-    // never waits.  A single ticket counter would serialise the tiles on one
-    // device-coherent atomic.
-    if (tid == 0) s_tile = blockIdx.x;
+    // The tile comes from the workgroup id rather than a ticket counter, which
+    // would serialise the tiles on one device-coherent atomic.
+    if (tid == 0) s_tile = (uint32_t)tile_of_block(blockIdx.x, gridDim.x);
     for (int i = tid; i < kPassWaves * kRadix; i += kPassThreads) {
         (&s_cnt[0][0])[i] = 0;
         s_match[i] = 0;

@@ -17,7 +17,7 @@ import torch
 from . import native as sfg
 
 D_IN = 10      # [is_pba, is_kron, log2(n)/20, m/8, 2p, W00, W01, W10, W11, k/20]
-D_OUT = 34     # 32 log-frequency bins, gamma, closed-wedge fraction
+D_OUT = 34     # 32 degree-bin shares, log(gamma - 1), closed-wedge fraction
 GAMMA_COL = 32
 
 
@@ -38,14 +38,17 @@ def features(rows):
 
 
 def targets(rows, hist, gamma, closed, samples):
-    """(Y, mask): log(1e-6 + bin share), gamma, closed share; missing values masked."""
+    """(Y, mask): share of vertices per degree bin, log(gamma - 1), closed
+    share; missing values masked.  The estimated exponent is heavy-tailed
+    (nearly regular graphs give very large values); log(gamma - 1), the log
+    of the tail index, is the smooth quantity to regress on."""
     n = np.array([r["n"] if r["kind"] == "pba" else r["n0"] ** r["k"] for r in rows], np.float64)
     Y = np.zeros((len(rows), D_OUT), np.float32)
     M = np.ones((len(rows), D_OUT), np.float32)
-    Y[:, :32] = np.log(1e-6 + hist / n[:, None])
+    Y[:, :32] = hist / n[:, None]
     g = np.asarray(gamma, np.float64)
-    ok = np.isfinite(g)
-    Y[:, GAMMA_COL] = np.where(ok, g, 0)
+    ok = np.isfinite(g) & (g > 1)
+    Y[:, GAMMA_COL] = np.log(np.where(ok, g, 2.0) - 1.0)
     M[:, GAMMA_COL] = ok
     c = np.asarray(closed, np.float64)
     Y[:, 33] = np.where(c >= 0, c / max(samples, 1), 0)
@@ -123,15 +126,26 @@ class Surrogate:
             out.append(y.cpu().numpy() * self.sd + self.mu)
         return np.concatenate(out, 0)
 
-    def gamma_and_grad(self, X):
-        """Predicted gamma and d gamma / dX for a batch of feature rows."""
+    def log_tail_and_grad(self, X):
+        """Predicted u = log(gamma - 1) and du / dX for a batch of feature rows."""
         xb = torch.tensor(X).cuda()
         y = sfg.mlp_forward(self.shape, self.params, xb, self.ws)
         dy = torch.zeros_like(y)
         dy[:, GAMMA_COL] = 1.0
         _, dx = sfg.mlp_backward(self.shape, self.params, dy, self.ws, want_grad=False, want_dx=True)
-        g = y[:, GAMMA_COL].cpu().numpy() * self.sd[GAMMA_COL] + self.mu[GAMMA_COL]
-        return g, dx.cpu().numpy() * self.sd[GAMMA_COL]
+        u = y[:, GAMMA_COL].cpu().numpy().astype(np.float64) * self.sd[GAMMA_COL] + self.mu[GAMMA_COL]
+        return u, dx.cpu().numpy().astype(np.float64) * self.sd[GAMMA_COL]
+
+    def gamma_and_grad(self, X):
+        """Predicted gamma and d gamma / dX for a batch of feature rows."""
+        u, du = self.log_tail_and_grad(X)
+        e = np.exp(u)
+        return 1.0 + e, du * e[:, None]
+
+    @staticmethod
+    def gamma_of(Y):
+        """Exponent from the target encoding."""
+        return 1.0 + np.exp(np.asarray(Y)[:, GAMMA_COL].astype(np.float64))
 
 
 # ----------------------------------------------------------------------------- inversion
@@ -160,20 +174,23 @@ class Judge:
         return float(np.mean(vals))
 
 
-def invert(model, target, k, restarts=16, iters=60, lr=0.05, seed=0, bounds=(0.03, 0.97)):
-    """Projected gradient descent on (a, b) so that the predicted exponent
-    equals `target`; returns the candidates ordered by predicted error."""
+def invert(model, target, k, restarts=16, iters=40, damping=0.5, max_step=0.1, seed=0, bounds=(0.03, 0.97)):
+    """Solve predicted gamma(a, b) = target from several random starts by
+    damped minimum-norm Newton steps on u = log(gamma - 1), projected onto
+    the box; returns the candidates ordered by predicted error and their
+    predicted exponents."""
     rng = np.random.default_rng(seed)
     ab = rng.uniform(bounds[0], bounds[1], size=(restarts, 2))
+    ut = math.log(target - 1.0)
     for _ in range(iters):
         X = features([kron_row(a, b, k, 0) for a, b in ab])
-        g, dX = model.gamma_and_grad(X)
-        err = g - target
+        u, dX = model.log_tail_and_grad(X)
         # x5..x8 = (a, 1-a, b, 1-b): chain rule to (a, b)
-        da = dX[:, 5] - dX[:, 6]
-        db = dX[:, 7] - dX[:, 8]
-        step = np.stack([err * da, err * db], 1)
-        ab = np.clip(ab - lr * step, *bounds)
+        grad = np.stack([dX[:, 5] - dX[:, 6], dX[:, 7] - dX[:, 8]], 1)
+        step = damping * (u - ut)[:, None] * grad / ((grad * grad).sum(1, keepdims=True) + 1e-9)
+        norm = np.sqrt((step * step).sum(1, keepdims=True))
+        step *= np.minimum(1.0, max_step / np.maximum(norm, 1e-12))
+        ab = np.clip(ab - step, *bounds)
     X = features([kron_row(a, b, k, 0) for a, b in ab])
     g, _ = model.gamma_and_grad(X)
     order = np.argsort(np.abs(g - target))
@@ -193,12 +210,21 @@ def search_generator_only(judge, target, tol, budget=40, seed=0):
 
 
 def search_with_surrogate(model, judge, target, tol, budget=40, seed=0):
-    """Surrogate proposals judged by the generator, best first; falls back to
-    the generator-only search for the remaining budget."""
+    """Surrogate-proposed parameters, each judged by one generator run.  After
+    a miss the gap between the measured and the predicted log(gamma - 1) is
+    added to a running correction and the surrogate is inverted again for the
+    corrected target; returns (accepted, calls)."""
     calls0 = judge.calls
-    cands, _ = invert(model, target, judge.k, seed=seed)
-    for a, b in cands[:4]:
-        if abs(judge.gamma(a, b) - target) <= tol:
+    shift = 0.0
+    r = 0
+    while judge.calls - calls0 < budget:
+        t_model = 1.0 + math.exp(math.log(target - 1.0) - shift)
+        cands, pred = invert(model, t_model, judge.k, seed=seed * 1000 + r)
+        a, b = cands[0]
+        g = judge.gamma(a, b)
+        if abs(g - target) <= tol:
             return True, judge.calls - calls0
-    ok, more = search_generator_only(judge, target, tol, budget - (judge.calls - calls0), seed)
-    return ok, judge.calls - calls0
+        if math.isfinite(g) and g > 1:
+            shift += math.log(g - 1.0) - math.log(pred[0] - 1.0)
+        r += 1
+    return False, judge.calls - calls0

@@ -16,12 +16,16 @@ def _pba_twice(sfg, c):
     E = c["n"] * c["m"]
     ws = sfg.workspace(sfg.pba_workspace_bytes(c["n"], c["m"], c["num_parts"]))
     outs = []
-    for fill, stream in ((0xFF, None), (0x00, torch.cuda.Stream())):
-        ws.fill_(fill)
-        src = torch.empty(E, dtype=torch.int32, device="cuda")
-        dst = torch.empty(E, dtype=torch.int32, device="cuda")
-        with torch.cuda.stream(stream) if stream is not None else torch.cuda.stream(torch.cuda.current_stream()):
-            sfg.pba_generate(c["n"], c["m"], c["num_parts"], c["p_inter"], seed=c["seed"], src=src, dst=dst, ws=ws)
+    for fill, stream in ((0xFF, torch.cuda.current_stream()), (0x00, torch.cuda.Stream())):
+        # The poisoning fill runs on the same stream as the call: a fill left
+        # running on another stream would race with the generator.
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            ws.fill_(fill)
+            src = torch.empty(E, dtype=torch.int32, device="cuda")
+            dst = torch.empty(E, dtype=torch.int32, device="cuda")
+            sfg.pba_generate(c["n"], c["m"], c["num_parts"], c["p_inter"], seed=c["seed"], src=src, dst=dst, ws=ws,
+                             stream=stream)
         torch.cuda.synchronize()
         assert sfg.device_error() == 0
         outs.append((src, dst))

@@ -15,8 +15,8 @@ def trained():
     rows = [sg.kron_row(a, b, k, 31, graph_id=i) for i, (a, b) in enumerate(rng.uniform(0.03, 0.97, size=(3072, 2)))]
     Y, M = sg.generate_dataset(rows, samples=2000, stat_seed=5, max_batch_edges=1 << 26)
     X = sg.features(rows)
-    model = sg.Surrogate(batch=512, seed=1)
-    hist = model.fit(X[:2560], Y[:2560], M[:2560], epochs=60, lr=2e-3)
+    model = sg.Surrogate(batch=128, seed=1)
+    hist = model.fit(X[:2560], Y[:2560], M[:2560], epochs=100, lr=2e-3)
     return sg, model, X, Y, M, hist, k
 
 
@@ -26,18 +26,24 @@ def test_training_converges(trained):
 
 
 def test_heldout_gamma_prediction(trained):
+    # Held-out graphs: over the middle 60% of exponents the median error of
+    # the prediction is a small fraction of that range's width.
     sg, model, X, Y, M, hist, k = trained
-    pred = model.predict(X[2560:])
+    pred = sg.Surrogate.gamma_of(model.predict(X[2560:]))
     ok = M[2560:, sg.GAMMA_COL] > 0
-    err = np.abs(pred[ok, sg.GAMMA_COL] - Y[2560:][ok, sg.GAMMA_COL])
-    spread = Y[2560:][ok, sg.GAMMA_COL].std()
-    assert np.median(err) < 0.3 * spread, (np.median(err), spread)
+    y = sg.Surrogate.gamma_of(Y[2560:])[ok]
+    err = np.abs(pred[ok] - y)
+    lo, hi = np.quantile(y, [0.2, 0.8])
+    mid = (y > lo) & (y < hi)
+    assert np.median(err[mid]) < 0.05 * (hi - lo), (np.median(err[mid]), lo, hi)
 
 
 def test_inversion_beats_generator_only_search(trained):
     sg, model, X, Y, M, hist, k = trained
-    g = Y[M[:, sg.GAMMA_COL] > 0, sg.GAMMA_COL]
-    targets = np.quantile(g, [0.2, 0.4, 0.6, 0.8])
+    # Exponents of the usual scale-free range, all inside the training data.
+    g = sg.Surrogate.gamma_of(Y)[M[:, sg.GAMMA_COL] > 0]
+    targets = np.array([2.2, 2.5, 2.8, 3.1])
+    assert g.min() < targets.min() and targets.max() < g.max()
     judge = sg.Judge(k=k, seeds=(31,), samples=2000)
     tol = 0.05
     with_s, without = [], []
