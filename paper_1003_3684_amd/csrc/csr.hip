@@ -45,6 +45,8 @@ constexpr int kFinTile = kFinThreads * kFinItems;
 
 constexpr int kScanChunk = 4096;  // vertices per chunk of the row fill scan
 constexpr int kPrepUnroll = 4;    // keys per thread in flight in the histogram pass
+constexpr int kPrepCopies = 4;    // interleaved copies of each LDS histogram
+constexpr int kPrepBlocksPerCu = 4;
 
 constexpr uint64_t kNoRow = ~0ull;
 
@@ -108,9 +110,13 @@ struct PrepArgs {
 
 template <typename IdT, typename KeyT, bool SYM>
 __global__ __launch_bounds__(256) void csr_prepare(PrepArgs a) {
-    __shared__ uint32_t s_h[8 * kRadix];
-    for (int i = threadIdx.x; i < 8 * kRadix; i += 256) s_h[i] = 0;
+    // kPrepCopies interleaved copies of every histogram, lane l counting in
+    // copy l mod kPrepCopies: skewed digits (one value drawn by many lanes of
+    // a wave) would otherwise serialise the LDS atomics on one address.
+    __shared__ uint32_t s_h[8 * kRadix * kPrepCopies];
+    for (int i = threadIdx.x; i < 8 * kRadix * kPrepCopies; i += 256) s_h[i] = 0;
     __syncthreads();
+    const uint32_t copy = threadIdx.x % kPrepCopies;
     const IdT *src = static_cast<const IdT *>(a.src), *dst = static_cast<const IdT *>(a.dst);
     // kPrepUnroll keys per thread are loaded before any is counted, so that
     // enough loads are in flight to cover the memory latency.
@@ -125,12 +131,17 @@ __global__ __launch_bounds__(256) void csr_prepare(PrepArgs a) {
 #pragma unroll
         for (int u = 0; u < kPrepUnroll; ++u) {
             if (i0 + (uint64_t)u * 256 >= a.N) break;
-            for (int p = 0; p < a.passes; ++p) atomicAdd(&s_h[p * kRadix + (uint32_t)((k[u] >> (8 * p)) & 255)], 1u);
+            for (int p = 0; p < a.passes; ++p)
+                atomicAdd(&s_h[(p * kRadix + (uint32_t)((k[u] >> (8 * p)) & 255)) * kPrepCopies + copy], 1u);
         }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < a.passes * kRadix; i += 256)
-        if (s_h[i]) atomicAdd((unsigned long long *)&a.ghist[i], (unsigned long long)s_h[i]);
+    for (int i = threadIdx.x; i < a.passes * kRadix; i += 256) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int c = 0; c < kPrepCopies; ++c) t += s_h[i * kPrepCopies + c];
+        if (t) atomicAdd((unsigned long long *)&a.ghist[i], (unsigned long long)t);
+    }
 }
 
 // Exclusive scan of every pass's digit histogram -> bucket bases.
@@ -182,17 +193,19 @@ struct PassArgs {
 // BOUND: the input keys are ordered by destination; mark the first position
 // of every destination run in csc.
 template <typename IdT, typename KeyT, bool SYM, bool FIRST, bool BOUND>
-__global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
+__global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassArgs a) {
     // s_keys holds the tile's keys in digit order after ranking; during the
     // ranking its first 16 KB serve as the per-wave lane-match tables.
     __shared__ KeyT s_keys[kPassTile];
     // 16-bit counters keep the block at about 38 KB of LDS: four tiles per CU.
     __shared__ uint16_t s_cnt[kPassWaves][kRadix];
     __shared__ uint16_t s_off[kRadix];
+    __shared__ uint16_t s_tot[kRadix];
     __shared__ uint64_t s_gpos[kRadix];
     __shared__ uint64_t s_tmp[4];
     __shared__ uint32_t s_tile;
     static_assert(sizeof(KeyT) * kPassTile >= sizeof(uint64_t) * kPassWaves * kRadix, "match tables do not fit");
+    static_assert(kPassThreads == 2 * kRadix, "the look-back pairs two lanes with every digit");
     uint64_t *s_match = reinterpret_cast<uint64_t *>(s_keys) + 0;  // [kPassWaves][256]
 
     const int tid = threadIdx.x;
@@ -283,61 +296,79 @@ __global__ __launch_bounds__(kPassThreads) void radix_pass(PassArgs a) {
             acc += c;
         }
         cnt = acc;
-    }
-    uint64_t tot;
-    const uint64_t ex = block_exclusive_scan_256(cnt, s_tmp, &tot);
-
-    // Decoupled look-back: the number of keys with digit d in earlier tiles.
-    if (tid < kRadix) {
-        s_off[tid] = (uint16_t)ex;
-        uint64_t *st = a.status + tile * kRadix + tid;
-        uint64_t prefix = 0;
-        if (tile == 0) {
-            store_agent(st, status_word(a.tag, kFlagIncl, cnt));
-        } else {
-            store_agent(st, status_word(a.tag, kFlagAgg, cnt));
-            // Look back over kLookWindow predecessors per round trip: read
-            // them together, then add counts from the nearest one back until
-            // an inclusive prefix; a predecessor not yet published is
-            // re-read until it is.
-            uint64_t j = tile;  // tiles below j are still to be examined
-            bool done = false;
-            while (!done) {
-                uint64_t v[kLookWindow];
-#pragma unroll
-                for (int i = 0; i < kLookWindow; ++i)
-                    v[i] = (j > (uint64_t)i) ? load_agent(a.status + (j - 1 - i) * kRadix + tid) : 0;
-#pragma unroll
-                for (int i = 0; i < kLookWindow; ++i) {
-                    if (done || j <= (uint64_t)i) break;
-                    const uint64_t *pj = a.status + (j - 1 - i) * kRadix + tid;
-                    uint32_t spins = 0;
-                    while ((uint32_t)(v[i] >> 58) != a.tag) {
-                        if (++spins > kSpinLimit || ((spins & 1023) == 0 && load_agent(a.err) != 0)) {
-                            raise_device_error(a.err, DEVERR_LOOKBACK);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                        v[i] = load_agent(pj);
-                    }
-                    prefix += v[i] & ((1ull << 56) - 1);
-                    if (((v[i] >> 56) & 3) == kFlagIncl || (uint32_t)(v[i] >> 58) != a.tag || j - 1 - i == 0)
-                        done = true;
-                }
-                j = j > (uint64_t)kLookWindow ? j - kLookWindow : 0;
-                if (j == 0) done = true;
-            }
-            store_agent(st, status_word(a.tag, kFlagIncl, prefix + cnt));
-        }
-        s_gpos[tid] = a.gbase[tid] + prefix - ex;
+        s_tot[tid] = (uint16_t)acc;
     }
     __syncthreads();
 
-    // Scatter into LDS in digit order, then write digit runs out coalesced.
+    // Decoupled look-back, two lanes per digit: lane pair (2d, 2d+1) of the
+    // block handles digit d and reads kLookWindow predecessors per lane, so
+    // one round trip covers 2 kLookWindow earlier tiles.  The even lane
+    // publishes: the tile's own count first, its inclusive prefix once known.
+    const uint32_t dg = (uint32_t)tid >> 1, half = (uint32_t)tid & 1u;
+    uint64_t *st = a.status + tile * kRadix + dg;
+    const uint64_t my_cnt = s_tot[dg];
+    if (half == 0) store_agent(st, status_word(a.tag, tile == 0 ? kFlagIncl : kFlagAgg, my_cnt));
+
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan_256(cnt, s_tmp, &tot);
+    if (tid < kRadix) s_off[tid] = (uint16_t)ex;
+    __syncthreads();
+
+    // Scatter into LDS in digit order (the local order needs no global
+    // offsets, and the keys leave the registers before the look-back).
 #pragma unroll
     for (int i = 0; i < kPassItems; ++i)
         if (d[i] < kRadix) s_keys[s_off[d[i]] + s_cnt[w][d[i]] + r[i]] = k[i];
+
+    uint64_t prefix = 0;
+    if (tile > 0) {
+        uint64_t j = tile;  // tiles below j are still to be examined
+        for (;;) {
+            // This lane's predecessors: j - 1 - (half kLookWindow + i).  One
+            // beyond tile 0 reads as an inclusive zero, which ends the walk.
+            uint64_t v[kLookWindow];
+#pragma unroll
+            for (int i = 0; i < kLookWindow; ++i) {
+                const uint64_t back = (uint64_t)half * kLookWindow + i;
+                v[i] = j > back ? load_agent(a.status + (j - 1 - back) * kRadix + dg)
+                                : status_word(a.tag, kFlagIncl, 0);
+            }
+            uint64_t sum = 0;
+            bool found = false;
+#pragma unroll
+            for (int i = 0; i < kLookWindow; ++i) {
+                if (found) break;
+                const uint64_t back = (uint64_t)half * kLookWindow + i;
+                uint32_t spins = 0;
+                while ((uint32_t)(v[i] >> 58) != a.tag) {
+                    if (++spins > kSpinLimit || ((spins & 1023) == 0 && load_agent(a.err) != 0)) {
+                        raise_device_error(a.err, DEVERR_LOOKBACK);
+                        v[i] = status_word(a.tag, kFlagIncl, 0);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    v[i] = load_agent(a.status + (j - 1 - back) * kRadix + dg);
+                }
+                sum += v[i] & ((1ull << 56) - 1);
+                found = ((v[i] >> 56) & 3) == kFlagIncl;
+            }
+            // Combine the pair: the even lane's predecessors are the nearer.
+            const uint64_t sum0 = __shfl(sum, (int)(lane & ~1u), 64), sum1 = __shfl(sum, (int)(lane | 1u), 64);
+            const int f0 = __shfl((int)found, (int)(lane & ~1u), 64), f1 = __shfl((int)found, (int)(lane | 1u), 64);
+            prefix += sum0;
+            if (f0) break;
+            prefix += sum1;
+            if (f1) break;
+            j -= 2 * kLookWindow;  // j > 2 kLookWindow, else a sentinel had ended the walk
+        }
+        if (half == 0) store_agent(st, status_word(a.tag, kFlagIncl, prefix + my_cnt));
+    }
+    if (half == 0) s_gpos[dg] = prefix;
     __syncthreads();
+    if (tid < kRadix) s_gpos[tid] = a.gbase[tid] + s_gpos[tid] - ex;
+    __syncthreads();
+
+    // Write the digit runs out, coalesced.
     const uint64_t rem = a.N - tile_base;
     const uint32_t nvalid = rem < (uint64_t)kPassTile ? (uint32_t)rem : (uint32_t)kPassTile;
     KeyT *out = static_cast<KeyT *>(a.out);
@@ -739,7 +770,9 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
 
     if (P.N > 0) {
         PrepArgs pa{P.E, P.N, src, dst, ghist, P.db, P.passes};
-        const int pg = fill_grid(P.N);
+        // Every histogram workgroup stays resident (32 KB of LDS each).
+        const int pg = (int)std::max<uint64_t>(1, std::min<uint64_t>((P.N + 255) / 256,
+                                                                      (uint64_t)device_cu_count() * kPrepBlocksPerCu));
         if (P.sym)
             { ProfScope _ps("csr_prepare", s); csr_prepare<IdT, KeyT, true><<<pg, 256, 0, s>>>(pa); }
         else
