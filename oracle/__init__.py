@@ -56,6 +56,7 @@ def _load():
         "orc_gamma_mle": (C.c_double, [C.c_uint64, u64p, C.c_uint64]),
         "orc_simple_csr": (C.c_int64, [C.c_uint64, C.c_uint64, i64p, i64p, u64p, i64p]),
         "orc_wedge_closed": (C.c_int64, [C.c_uint64, u64p, i64p, C.c_uint32, C.c_uint64, C.c_uint32]),
+        "orc_path_stats": (None, [C.c_uint64, u64p, i64p, i64p, C.c_uint32, u64p, u64p, u64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -227,6 +228,19 @@ def wedge_closed(n, row_ptr, col, num_samples, seed, graph_id=0):
     if col.size == 0:
         col = np.zeros(1, np.int64)
     return int(_load().orc_wedge_closed(n, row_ptr, col, num_samples, seed, graph_id))
+
+
+def path_stats(n, row_ptr, col, sources):
+    """(sum of distances, reachable pairs, largest distance) of breadth-first
+    searches from `sources` over the CSR graph (Results, Table 2)."""
+    row_ptr = np.ascontiguousarray(row_ptr, np.uint64)
+    col = np.ascontiguousarray(col, np.int64)
+    if col.size == 0:
+        col = np.zeros(1, np.int64)
+    src = np.ascontiguousarray(sources, np.int64)
+    out = np.zeros(3, np.uint64)
+    _load().orc_path_stats(n, row_ptr, col, src, src.size, out[0:1], out[1:2], out[2:3])
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def graph_stats(n, src, dst, num_samples, seed, graph_id=0):

@@ -550,3 +550,44 @@ int64_t orc_wedge_closed(uint64_t n, const uint64_t *row_ptr, const int64_t *col
     free(pre);
     return closed;
 }
+
+/* ------------------------------------------------------------------------
+ * Sampled path statistics (Results, Table 2: average shortest-path length and
+ * diameter estimated by sampling).  A breadth-first search from every given
+ * source over the CSR graph (unweighted; the caller passes the simple
+ * undirected CSR).  Outputs: the sum of d(s, v) and the number of pairs over
+ * all sources s and vertices v != s reachable from s, and the largest such
+ * distance (the sampled eccentricity maximum, the diameter estimate).
+ * ---------------------------------------------------------------------- */
+void orc_path_stats(uint64_t n, const uint64_t *row_ptr, const int64_t *col, const int64_t *sources,
+                    uint32_t num_sources, uint64_t *sum_out, uint64_t *pairs_out, uint64_t *max_out)
+{
+    int64_t *dist = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (n ? n : 1));
+    uint64_t sum = 0, pairs = 0, mx = 0;
+    for (uint32_t i = 0; i < num_sources; ++i) {
+        for (uint64_t v = 0; v < n; ++v) dist[v] = -1;
+        int64_t s = sources[i];
+        uint64_t head = 0, tail = 0;
+        dist[s] = 0;
+        queue[tail++] = s;
+        while (head < tail) {
+            int64_t u = queue[head++];
+            for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; ++e) {
+                int64_t x = col[e];
+                if (dist[x] < 0) {
+                    dist[x] = dist[u] + 1;
+                    queue[tail++] = x;
+                    sum += (uint64_t)dist[x];
+                    pairs += 1;
+                    if ((uint64_t)dist[x] > mx) mx = (uint64_t)dist[x];
+                }
+            }
+        }
+    }
+    *sum_out = sum;
+    *pairs_out = pairs;
+    *max_out = mx;
+    free(dist);
+    free(queue);
+}

@@ -484,3 +484,61 @@ def test_wedges_estimate_transitivity(orc):
     closed = orc.wedge_closed(n, rp, col, N, 17)
     sd = math.sqrt(N * tau * (1 - tau))
     assert abs(closed - N * tau) < 5 * sd, (closed, N * tau)
+
+
+# --------------------------------------------------------------------------- sampled path statistics
+def _csr_of_undirected(n, pairs):
+    """Simple undirected CSR of an explicit edge list (numpy, independent of the oracle)."""
+    if len(pairs):
+        a = np.array(pairs, np.int64)
+        u = np.concatenate([a[:, 0], a[:, 1]])
+        v = np.concatenate([a[:, 1], a[:, 0]])
+        keep = u != v
+        key = np.unique(u[keep] * n + v[keep])
+        u, v = key // n, key % n
+    else:
+        u = v = np.zeros(0, np.int64)
+    rp = np.zeros(n + 1, np.uint64)
+    np.add.at(rp, u + 1, 1)
+    return np.cumsum(rp).astype(np.uint64), v.astype(np.int64)
+
+
+def test_path_stats_closed_forms(orc):
+    # path P_n from one end: distances 1..n-1
+    n = 50
+    rp, col = _csr_of_undirected(n, [(i, i + 1) for i in range(n - 1)])
+    assert orc.path_stats(n, rp, col, [0]) == (n * (n - 1) // 2, n - 1, n - 1)
+    # cycle C_n: two vertices at every distance below n/2, one at n/2 when n is even
+    for n in (9, 10):
+        rp, col = _csr_of_undirected(n, [(i, (i + 1) % n) for i in range(n)])
+        h = (n - 1) // 2
+        want = 2 * h * (h + 1) // 2 + (n // 2 if n % 2 == 0 else 0)
+        assert orc.path_stats(n, rp, col, [3]) == (want, n - 1, n // 2)
+    # star: centre 0; a leaf sees the centre at 1 and the other leaves at 2
+    n = 12
+    rp, col = _csr_of_undirected(n, [(0, i) for i in range(1, n)])
+    assert orc.path_stats(n, rp, col, [0]) == (n - 1, n - 1, 1)
+    assert orc.path_stats(n, rp, col, [5]) == (1 + 2 * (n - 2), n - 1, 2)
+    # hypercube Q_d: distance = Hamming distance, summing to d 2^(d-1)
+    d = 7
+    n = 1 << d
+    rp, col = _csr_of_undirected(n, [(v, v ^ (1 << b)) for v in range(n) for b in range(d)])
+    assert orc.path_stats(n, rp, col, [0, 77]) == (2 * d * (1 << (d - 1)), 2 * (n - 1), d)
+    # two components: only reachable pairs count
+    rp, col = _csr_of_undirected(6, [(0, 1), (1, 2), (3, 4)])
+    assert orc.path_stats(6, rp, col, [0, 3, 5]) == (1 + 2 + 1, 3, 2)
+
+
+def test_path_stats_match_scipy_bfs(orc):
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import shortest_path
+    rng = np.random.default_rng(8)
+    for n, m in ((60, 90), (200, 260), (300, 2000)):
+        pairs = list(zip(rng.integers(0, n, m), rng.integers(0, n, m)))
+        rp, col = _csr_of_undirected(n, pairs)
+        A = csr_matrix((np.ones(col.size), col, rp.astype(np.int64)), shape=(n, n))
+        srcs = rng.integers(0, n, 7)
+        D = shortest_path(A, method="D", unweighted=True, indices=srcs)
+        fin = np.isfinite(D) & (D > 0)
+        want = (int(D[fin].sum()), int(fin.sum()), int(D[fin].max()) if fin.any() else 0)
+        assert orc.path_stats(n, rp, col, srcs) == want
