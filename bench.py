@@ -75,10 +75,23 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 23, help="edges in the CPU-oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="edges in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the PBA and ensemble extras")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 2 GiB device-to-device copy three times (the reference kernel of known "
+                         "size for scaling the HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(1 << 28, dtype=torch.int64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read_per_copy": a.numel() * 8,
+                          "bytes_written_per_copy": a.numel() * 8, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design note, "
               "not a measured path.", file=sys.stderr)
@@ -178,7 +191,8 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_extras:
-        result["extras"] = {"pba": _bench_pba(sfg, wl, torch), "ensemble": _bench_ensemble(sfg, wl, torch)}
+        result["extras"] = {"pba": _bench_pba(sfg, wl, torch), "ensemble": _bench_ensemble(sfg, wl, torch),
+                            "kron_enumerate": _bench_enumerate(sfg, wl, torch), "mlp": _bench_mlp(sfg, torch)}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_sample)
     print(json.dumps(result), flush=True)
@@ -220,6 +234,68 @@ def _bench_pba(sfg, wl, torch, reps=3):
     del src, dst, ws, rp, col
     torch.cuda.empty_cache()
     return out
+
+
+def _bench_enumerate(sfg, wl, torch, k=9, reps=5):
+    """The paper's deterministic Kronecker power of the Fig. 2 seed (11 edges,
+    5 vertices) at 9 levels: 11^9 edges, int32 ids; bound by HBM writes."""
+    E = 11 ** k
+    src = torch.empty(E, dtype=torch.int32, device="cuda")
+    dst = torch.empty(E, dtype=torch.int32, device="cuda")
+    W = wl.FIG2_SEED.astype("float32")
+
+    def run():
+        sfg.kron_generate(5, W, k, E, mode=sfg.KRON_ENUMERATE, src=src, dst=dst)
+
+    run()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        run()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    gbs = 8 * E / (ms / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"workload": f"fig2_seed_k{k}", "edges": E, "ms": ms, "edges_per_s": E / (ms / 1e3),
+            "write_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+
+
+def _bench_mlp(sfg, torch, batch=4096, steps=50):
+    """One surrogate training step (forward, masked MSE gradient, backward,
+    Adam) at batch 4,096 on the 10 -> 256 x 3 -> 34 network."""
+    shape = sfg.mlp_shape(10, 256, 34, 3)
+    P = sfg.mlp_param_count(shape)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    params = (torch.randn(P, device="cuda", generator=g) * 0.05).contiguous()
+    m, v = torch.zeros_like(params), torch.zeros_like(params)
+    x = torch.randn(batch, 10, device="cuda", generator=g)
+    t = torch.randn(batch, 34, device="cuda", generator=g)
+    ws = sfg.workspace(sfg.mlp_workspace_bytes(shape, batch))
+    lws = sfg.workspace(4 * batch)
+
+    def step(i):
+        y = sfg.mlp_forward(shape, params, x, ws)
+        dy, _ = sfg.mlp_mse_grad(y, t, lws)
+        grad, _ = sfg.mlp_backward(shape, params, dy, ws)
+        sfg.adam_step(params, grad, m, v, i + 1, lr=1e-3)
+
+    step(0)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(steps):
+        step(i + 1)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / steps
+    macs = 10 * 256 + 2 * 256 * 256 + 256 * 34
+    flops = 3 * 2 * batch * macs  # forward, input gradients, weight gradients
+    return {"batch": batch, "ms_per_step": ms, "samples_per_s": batch / (ms / 1e3),
+            "tflops": flops / (ms / 1e3) / 1e12, "mfma_peak_tflops_bf16": 2500.0,
+            "note": "launch-bound: a 256-wide network is far below the matrix-core roofline"}
 
 
 def _bench_ensemble(sfg, wl, torch, samples=10_000, stat_seed=5, max_batch_edges=1 << 30):

@@ -79,7 +79,7 @@ int sfg_device_error(void *stream, uint32_t *code);
  * milliseconds; sfg_profile_reset forgets all records.  Kernel names:
  * "kron_sample", "kron_enumerate", "csr_prepare", "radix_pass",
  * "csr_finish", "csr_rowfill", "degree_hist", "pba_draw1", "pba_resolve",
- * "pba_count", "pba_scan", "pba_draw2", "pba_substitute". */
+ * "pba_count", "pba_scan", "pba_draw2", "pba_substitute", "path_level". */
 int sfg_profile_enable(int on);
 int sfg_profile_reset(void);
 int sfg_profile_query(const char *name, uint64_t *launches, double *total_ms);
@@ -212,6 +212,34 @@ size_t graph_stats_workspace_bytes(uint64_t n, uint64_t num_edges, int id_bytes)
 int graph_stats(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes, uint32_t num_samples,
                 uint64_t seed, uint32_t graph_id, uint64_t *degree_hist32, double *gamma, int64_t *closed,
                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * path_stats -- sampled shortest-path statistics (Results, Table 2: average
+ * path length and diameter, both estimated by sampling).
+ *
+ * Breadth-first searches over the graph in CSR form from each given source:
+ * out[0] = sum of d(s, v), out[1] = number of pairs, both over all sources s
+ * and all vertices v != s reachable from s; out[2] = the largest such d (the
+ * diameter estimate).  The average path length is out[0] / out[1].  Each
+ * level looks at the neighbours listed in the CSR, so the CSR must be
+ * symmetric (an undirected graph, e.g. edges_to_csr with
+ * SFG_CSR_SYMMETRIZE | SFG_CSR_SIMPLE); repeated sources count once each.
+ *
+ * n, row_ptr:    device, n + 1 row starts (u64).
+ * col:           device, row_ptr[n] ids (id_bytes wide), each < n.
+ * sources:       host, num_sources vertex ids in [0, n) (the sample; read
+ *                before the call returns).
+ * out:           device, 3 u64.
+ * workspace:     device, path_stats_workspace_bytes(n) (32 B per vertex).
+ * The call searches 64 sources at a time and waits for the stream after
+ * every level to decide whether the search is over, so it returns with the
+ * work done.
+ * Errors: EINVAL (n == 0, bad id_bytes, NULL buffers, a source outside
+ * [0, n)); ENOSPACE.
+ * ---------------------------------------------------------------------- */
+size_t path_stats_workspace_bytes(uint64_t n);
+int path_stats(uint64_t n, const uint64_t *row_ptr, const void *col, int id_bytes, const int64_t *sources,
+               uint32_t num_sources, uint64_t *out, void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * ensemble_generate -- a batched ensemble of graphs (PBA and Kronecker

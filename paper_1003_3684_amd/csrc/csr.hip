@@ -30,14 +30,13 @@
 namespace sfg {
 namespace {
 
-constexpr int kPassThreads = 512;
+constexpr int kPassThreads = 1024;
 constexpr int kPassItems = 8;
 constexpr int kPassTile = kPassThreads * kPassItems;  // keys per onesweep tile
 constexpr int kPassWaves = kPassThreads / 64;
 constexpr int kRadix = 256;
-constexpr int kLookWindow = 4;  // predecessors read per look-back round trip
-constexpr int kXcdCount = 8;     // workgroup b runs on XCD b mod 8
-constexpr int kXcdRun = 16;      // consecutive tiles given to one XCD
+constexpr int kLookWindow = 2;  // predecessors read per lane and look-back round trip
+constexpr int kLanesPerDigit = kPassThreads / kRadix;  // look-back lanes per digit
 
 constexpr int kFinThreads = 256;
 constexpr int kFinItems = 16;
@@ -159,22 +158,6 @@ template <typename T> __global__ void fill_kernel(T *p, uint64_t n, T v) {
 }
 
 // --------------------------------------------------------------------------- onesweep pass
-// Tile of workgroup b out of `tiles`.  Workgroups are dispatched in id order,
-// round-robin over the XCDs, and neighbouring tiles write neighbouring pieces
-// of every digit run: the cache line at the seam of two pieces is written
-// half by each.  Handing kXcdRun consecutive tiles to one XCD puts both
-// halves of most seams in the same L2, which then writes the line back once
-// and whole instead of twice in part.  Within each XCD the tile numbers still
-// rise with the dispatch order (the tail that does not fill a group keeps
-// tile = b), which is what keeps the look-back free of deadlock: the smallest
-// unfinished tile is always dispatched and waits for nothing.
-__device__ __forceinline__ uint64_t tile_of_block(uint64_t b, uint64_t tiles) {
-    constexpr uint64_t G = (uint64_t)kXcdCount * kXcdRun;
-    const uint64_t g0 = b / G * G;
-    if (g0 + G > tiles) return b;
-    const uint64_t j = b - g0;
-    return g0 + (j % kXcdCount) * kXcdRun + j / kXcdCount;
-}
 
 struct PassArgs {
     uint64_t E, N;
@@ -186,6 +169,7 @@ struct PassArgs {
     uint32_t *ticket;
     uint32_t *err;
     uint64_t *csc;          // column starts (BOUND passes only)
+    uint8_t *cmark;         // 1 where a column start was written (BOUND passes only)
     int wb, shift;          // wb: width of the destination field
     uint32_t tag;
 };
@@ -203,23 +187,23 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
     __shared__ uint16_t s_tot[kRadix];
     __shared__ uint64_t s_gpos[kRadix];
     __shared__ uint64_t s_tmp[4];
-    __shared__ uint32_t s_tile;
     static_assert(sizeof(KeyT) * kPassTile >= sizeof(uint64_t) * kPassWaves * kRadix, "match tables do not fit");
-    static_assert(kPassThreads == 2 * kRadix, "the look-back pairs two lanes with every digit");
+    static_assert(kPassThreads % kRadix == 0 && 64 % kLanesPerDigit == 0, "look-back lane groups");
     uint64_t *s_match = reinterpret_cast<uint64_t *>(s_keys) + 0;  // [kPassWaves][256]
 
     const int tid = threadIdx.x;
     const uint32_t lane = tid & 63;
     const int w = tid >> 6;
-    // The tile comes from the workgroup id rather than a ticket counter, which
-    // would serialise the tiles on one device-coherent atomic.
-    if (tid == 0) s_tile = (uint32_t)tile_of_block(blockIdx.x, gridDim.x);
     for (int i = tid; i < kPassWaves * kRadix; i += kPassThreads) {
         (&s_cnt[0][0])[i] = 0;
         s_match[i] = 0;
     }
     __syncthreads();
-    const uint64_t tile = s_tile;
+    // Tile = workgroup id.  Workgroups are dispatched in id order, so every
+    // tile this one waits for in the look-back was dispatched earlier and is
+    // running or done: the smallest unfinished tile never waits.  (A ticket
+    // counter would serialise the tiles on one device-coherent atomic.)
+    const uint64_t tile = blockIdx.x;
     const uint64_t tile_base = tile * kPassTile;
     const uint64_t wbase = tile_base + (uint64_t)w * 64 * kPassItems;
     const bool full = tile_base + kPassTile <= a.N;
@@ -251,7 +235,10 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
             KeyT prev = __shfl_up(k[i], 1, 64);
             if (lane == 0) prev = carry;
             carry = __shfl(k[i], 63, 64);
-            if (idx < a.N && (idx == 0 || (k[i] & mask) != (prev & mask))) a.csc[(uint64_t)(k[i] & mask)] = idx;
+            if (idx < a.N && (idx == 0 || (k[i] & mask) != (prev & mask))) {
+                a.csc[(uint64_t)(k[i] & mask)] = idx;
+                a.cmark[(uint64_t)(k[i] & mask)] = 1;
+            }
         }
     }
 
@@ -300,14 +287,14 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
     }
     __syncthreads();
 
-    // Decoupled look-back, two lanes per digit: lane pair (2d, 2d+1) of the
-    // block handles digit d and reads kLookWindow predecessors per lane, so
-    // one round trip covers 2 kLookWindow earlier tiles.  The even lane
-    // publishes: the tile's own count first, its inclusive prefix once known.
-    const uint32_t dg = (uint32_t)tid >> 1, half = (uint32_t)tid & 1u;
-    uint64_t *st = a.status + tile * kRadix + dg;
+    // Decoupled look-back with kLanesPerDigit consecutive lanes per digit:
+    // lane q of digit d's group reads kLookWindow predecessors, so one round
+    // trip covers kLanesPerDigit kLookWindow earlier tiles.  Lane 0 of the
+    // group publishes: the tile's own count first, its inclusive prefix once
+    // known.
+    const uint32_t dg = (uint32_t)tid / kLanesPerDigit, part = (uint32_t)tid % kLanesPerDigit;
     const uint64_t my_cnt = s_tot[dg];
-    if (half == 0) store_agent(st, status_word(a.tag, tile == 0 ? kFlagIncl : kFlagAgg, my_cnt));
+    if (part == 0) store_agent(a.status + tile * kRadix + dg, status_word(a.tag, tile == 0 ? kFlagIncl : kFlagAgg, my_cnt));
 
     uint64_t tot;
     const uint64_t ex = block_exclusive_scan_256(cnt, s_tmp, &tot);
@@ -324,12 +311,12 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
     if (tile > 0) {
         uint64_t j = tile;  // tiles below j are still to be examined
         for (;;) {
-            // This lane's predecessors: j - 1 - (half kLookWindow + i).  One
+            // This lane's predecessors: j - 1 - (part kLookWindow + i).  One
             // beyond tile 0 reads as an inclusive zero, which ends the walk.
             uint64_t v[kLookWindow];
 #pragma unroll
             for (int i = 0; i < kLookWindow; ++i) {
-                const uint64_t back = (uint64_t)half * kLookWindow + i;
+                const uint64_t back = (uint64_t)part * kLookWindow + i;
                 v[i] = j > back ? load_agent(a.status + (j - 1 - back) * kRadix + dg)
                                 : status_word(a.tag, kFlagIncl, 0);
             }
@@ -338,7 +325,7 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
 #pragma unroll
             for (int i = 0; i < kLookWindow; ++i) {
                 if (found) break;
-                const uint64_t back = (uint64_t)half * kLookWindow + i;
+                const uint64_t back = (uint64_t)part * kLookWindow + i;
                 uint32_t spins = 0;
                 while ((uint32_t)(v[i] >> 58) != a.tag) {
                     if (++spins > kSpinLimit || ((spins & 1023) == 0 && load_agent(a.err) != 0)) {
@@ -352,18 +339,24 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
                 sum += v[i] & ((1ull << 56) - 1);
                 found = ((v[i] >> 56) & 3) == kFlagIncl;
             }
-            // Combine the pair: the even lane's predecessors are the nearer.
-            const uint64_t sum0 = __shfl(sum, (int)(lane & ~1u), 64), sum1 = __shfl(sum, (int)(lane | 1u), 64);
-            const int f0 = __shfl((int)found, (int)(lane & ~1u), 64), f1 = __shfl((int)found, (int)(lane | 1u), 64);
-            prefix += sum0;
-            if (f0) break;
-            prefix += sum1;
-            if (f1) break;
-            j -= 2 * kLookWindow;  // j > 2 kLookWindow, else a sentinel had ended the walk
+            // Combine the group, nearest predecessors first.
+            const int lead = (int)(lane & ~(uint32_t)(kLanesPerDigit - 1));
+            bool done = false;
+#pragma unroll
+            for (int q = 0; q < kLanesPerDigit; ++q) {
+                const uint64_t sq = __shfl(sum, lead + q, 64);
+                const int fq = __shfl((int)found, lead + q, 64);
+                if (!done) {
+                    prefix += sq;
+                    done = fq != 0;
+                }
+            }
+            if (done) break;
+            j -= (uint64_t)kLanesPerDigit * kLookWindow;  // else a sentinel had ended the walk
         }
-        if (half == 0) store_agent(st, status_word(a.tag, kFlagIncl, prefix + my_cnt));
+        if (part == 0) store_agent(a.status + tile * kRadix + dg, status_word(a.tag, kFlagIncl, prefix + my_cnt));
     }
-    if (half == 0) s_gpos[dg] = prefix;
+    if (part == 0) s_gpos[dg] = prefix;
     __syncthreads();
     if (tid < kRadix) s_gpos[tid] = a.gbase[tid] + s_gpos[tid] - ex;
     __syncthreads();
@@ -384,8 +377,9 @@ struct FinArgs {
     uint64_t N, n;
     const void *keys;
     void *col;
-    uint64_t *rp;       // row starts in output (compacted) positions, kNoRow where no row starts
+    uint64_t *rp;       // row starts in output (compacted) positions, written where a row starts
     uint64_t *rp_raw;   // row starts in sorted positions, or null
+    uint8_t *mark;      // 1 where a row start was written (shared by rp and rp_raw)
     uint64_t *dups;     // [1] accumulated, or null
     uint64_t *status;   // [tiles] look-back words (SIMPLE)
     uint32_t *ticket;
@@ -419,11 +413,13 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish_plain(FinArgs a) {
             if (idx == 0 || row != (uint64_t)(prev >> a.wb)) {
                 a.rp[row] = idx;
                 if (a.rp_raw) a.rp_raw[row] = idx;
+                a.mark[row] = 1;
             }
             ndup += (idx > 0 && key == prev) ? 1u : 0u;
             if (idx == a.N - 1) {
                 a.rp[a.n] = a.N;
                 if (a.rp_raw) a.rp_raw[a.n] = a.N;
+                a.mark[a.n] = 1;
             }
         }
     }
@@ -527,6 +523,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
             if (idx == 0 || row != (uint64_t)(prev >> a.wb)) {
                 a.rp[row] = c;
                 if (a.rp_raw) a.rp_raw[row] = idx;
+                a.mark[row] = 1;
             }
             if (SIMPLE) {
                 if ((keep_bits >> j) & 1u) col[c++] = (IdT)(key & mask);
@@ -564,24 +561,48 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
             a.rp[a.n] = a.N;
         }
         if (a.rp_raw) a.rp_raw[a.n] = a.N;
+        a.mark[a.n] = 1;
     }
 }
 
 // --------------------------------------------------------------------------- row fill
-// rp[v] = kNoRow for rows without an entry; afterwards rp[v] = the start of
-// the next row that has one (a reverse running minimum; rp[n] is always set).
-__global__ __launch_bounds__(256) void rowfill_reduce(const uint64_t *rp, uint64_t n1, uint64_t *cmin) {
-    __shared__ uint64_t s[256];
-    const uint64_t c0 = (uint64_t)blockIdx.x * kScanChunk;
-    uint64_t m = kNoRow;
-    for (uint64_t v = c0 + threadIdx.x; v < c0 + kScanChunk && v < n1; v += 256) m = min(m, rp[v]);
-    s[threadIdx.x] = m;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (threadIdx.x < off) s[threadIdx.x] = min(s[threadIdx.x], s[threadIdx.x + off]);
-        __syncthreads();
+// mark[v] = 1 where rp[v] was written (a row with an entry; rp[n] always is).
+// Afterwards every rp[v] holds the value of the first marked row at or after
+// v.  Values at marked rows rise with the row, so that is a reverse running
+// minimum, taken per chunk of kScanChunk rows: the first marked value of every
+// chunk, an exclusive reverse scan over the chunks, then the chunk itself.
+// Unmarked rows are written without being read, and only the marks are
+// read for them.
+
+// Marks of rows v0 .. v0+15 (v0 a multiple of 16) as a 16-bit mask.
+__device__ __forceinline__ uint32_t load_marks16(const uint8_t *mark, uint64_t v0, uint64_t n1) {
+    if (v0 + 16 <= n1) {
+        const uint4 m = *reinterpret_cast<const uint4 *>(mark + v0);
+        const uint32_t w[4] = {m.x, m.y, m.z, m.w};
+        uint32_t bits = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bits |= ((w[q] >> (8 * b)) & 1u) << (4 * q + b);
+        return bits;
     }
-    if (threadIdx.x == 0) cmin[blockIdx.x] = s[0];
+    uint32_t bits = 0;
+    for (uint64_t v = v0; v < n1; ++v) bits |= (uint32_t)(mark[v] & 1u) << (uint32_t)(v - v0);
+    return bits;
+}
+
+__global__ __launch_bounds__(256) void rowfill_first(const uint64_t *rp, const uint8_t *mark, uint64_t n1,
+                                                     uint64_t *cfirst) {
+    __shared__ uint32_t s_first;
+    if (threadIdx.x == 0) s_first = ~0u;
+    __syncthreads();
+    constexpr int per = kScanChunk / 256;
+    const uint64_t c0 = (uint64_t)blockIdx.x * kScanChunk;
+    const uint64_t v0 = c0 + (uint64_t)threadIdx.x * per;
+    const uint32_t bits = v0 < n1 ? load_marks16(mark, v0, n1) : 0u;
+    if (bits) atomicMin(&s_first, (uint32_t)threadIdx.x * per + (uint32_t)__builtin_ctz(bits));
+    __syncthreads();
+    if (threadIdx.x == 0) cfirst[blockIdx.x] = s_first == ~0u ? kNoRow : rp[c0 + s_first];
 }
 
 // Exclusive reverse min-scan of the chunk minima (single block).
@@ -608,17 +629,21 @@ __global__ __launch_bounds__(1024) void rowfill_chunks(uint64_t *cmin, uint64_t 
     }
 }
 
-__global__ __launch_bounds__(256) void rowfill_apply(uint64_t *rp, uint64_t n1, const uint64_t *cnext) {
-    __shared__ uint64_t s[256];
+__global__ __launch_bounds__(256) void rowfill_apply(uint64_t *rp, const uint8_t *mark, uint64_t n1,
+                                                     const uint64_t *cnext) {
     constexpr int per = kScanChunk / 256;
+    // Thread t owns rows t*per .. t*per+per-1 of the chunk; the results go
+    // through LDS (one pad word per `per`) so the stores are coalesced.
+    __shared__ uint64_t s_out[kScanChunk + kScanChunk / per];
+    __shared__ uint64_t s[256];
     const uint64_t c0 = (uint64_t)blockIdx.x * kScanChunk;
     const uint64_t v0 = c0 + (uint64_t)threadIdx.x * per;
+    const uint32_t bits = v0 < n1 ? load_marks16(mark, v0, n1) : 0u;
     uint64_t x[per];
     uint64_t m = kNoRow;
 #pragma unroll
-    for (int j = per - 1; j >= 0; --j) {
-        const uint64_t v = v0 + j;
-        x[j] = v < n1 ? rp[v] : kNoRow;
+    for (int j = 0; j < per; ++j) {
+        x[j] = ((bits >> j) & 1u) ? rp[v0 + j] : kNoRow;  // marked rows only
         m = min(m, x[j]);
     }
     s[threadIdx.x] = m;
@@ -632,9 +657,13 @@ __global__ __launch_bounds__(256) void rowfill_apply(uint64_t *rp, uint64_t n1, 
     uint64_t run = min(cnext[blockIdx.x], threadIdx.x + 1 < 256 ? s[threadIdx.x + 1] : kNoRow);
 #pragma unroll
     for (int j = per - 1; j >= 0; --j) {
-        const uint64_t v = v0 + j;
         run = min(run, x[j]);
-        if (v < n1) rp[v] = run;
+        s_out[threadIdx.x * (per + 1) + j] = run;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kScanChunk; i += 256) {
+        const uint64_t v = c0 + i;
+        if (v < n1) rp[v] = s_out[(i / per) * (per + 1) + i % per];
     }
 }
 
@@ -673,8 +702,8 @@ struct Plan {
     bool sym, simple, hist, directed_hist;
     uint64_t pass_tiles, fin_tiles, chunks;
     // workspace carving
-    size_t off_keysA, off_keysB, off_status, off_ghist, off_gbase, off_tickets, off_indeg, off_rpraw, off_rpc,
-        off_cmin, off_fstatus, total;
+    size_t off_keysA, off_keysB, off_status, off_ghist, off_gbase, off_tickets, off_indeg, off_rpraw, off_mark,
+        off_cmark, off_cmin, off_fstatus, total;
 };
 
 Plan make_plan(uint64_t n, uint64_t E, int id_bytes, uint32_t flags, bool want_hist) {
@@ -712,7 +741,8 @@ Plan make_plan(uint64_t n, uint64_t E, int id_bytes, uint32_t flags, bool want_h
     p.off_tickets = take(16 * 4);
     p.off_indeg = take(p.directed_hist ? (n + 1) * 8 : 0);
     p.off_rpraw = take(want_hist && p.simple ? (n + 1) * 8 : 0);
-    p.off_rpc = take(0);
+    p.off_mark = take(n + 1);
+    p.off_cmark = take(p.directed_hist ? n + 1 : 0);
     p.off_cmin = take(std::max<uint64_t>(p.chunks, 1) * 8);
     p.off_fstatus = take(p.simple ? std::max<uint64_t>(p.fin_tiles, 1) * 8 : 0);
     p.total = o;
@@ -732,10 +762,16 @@ template <typename T> void fill(T *p, uint64_t n, T v, hipStream_t s) {
     }
 }
 
-void row_fill(uint64_t *rp, uint64_t n1, uint64_t *cmin, uint64_t chunks, hipStream_t s) {
-    { ProfScope _ps("csr_rowfill", s); rowfill_reduce<<<(int)chunks, 256, 0, s>>>(rp, n1, cmin); }
+void row_fill(uint64_t *rp, const uint8_t *mark, uint64_t n1, uint64_t *cmin, uint64_t chunks, hipStream_t s) {
+    { ProfScope _ps("csr_rowfill", s); rowfill_first<<<(int)chunks, 256, 0, s>>>(rp, mark, n1, cmin); }
     { ProfScope _ps("csr_rowfill", s); rowfill_chunks<<<1, 1024, 0, s>>>(cmin, chunks); }
-    { ProfScope _ps("csr_rowfill", s); rowfill_apply<<<(int)chunks, 256, 0, s>>>(rp, n1, cmin); }
+    { ProfScope _ps("csr_rowfill", s); rowfill_apply<<<(int)chunks, 256, 0, s>>>(rp, mark, n1, cmin); }
+}
+
+// Zero the mark bytes of rows [0, n1) (whole 32-bit words; the workspace
+// carving rounds every region up to 256 bytes).
+void clear_marks(uint8_t *mark, uint64_t n1, hipStream_t s) {
+    fill<uint32_t>(reinterpret_cast<uint32_t *>(mark), (n1 + 3) / 4, 0u, s);
 }
 
 template <typename IdT, typename KeyT>
@@ -751,6 +787,8 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
     uint64_t *csc = P.directed_hist ? reinterpret_cast<uint64_t *>(ws + P.off_indeg) : nullptr;
     uint64_t *rp_raw_ws = (P.hist && P.simple) ? reinterpret_cast<uint64_t *>(ws + P.off_rpraw) : nullptr;
     uint64_t *cmin = reinterpret_cast<uint64_t *>(ws + P.off_cmin);
+    uint8_t *mark = reinterpret_cast<uint8_t *>(ws + P.off_mark);
+    uint8_t *cmark = P.directed_hist ? reinterpret_cast<uint8_t *>(ws + P.off_cmark) : nullptr;
     uint64_t *fstatus = P.simple ? reinterpret_cast<uint64_t *>(ws + P.off_fstatus) : nullptr;
 
     // Clear counters, histograms and look-back words (fill kernels, so the
@@ -759,14 +797,16 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
     fill<uint32_t>(tickets, 16, 0, s);
     if (P.N) fill<uint64_t>(status, P.pass_tiles * kRadix, 0, s);
     if (fstatus && P.N) fill<uint64_t>(fstatus, P.fin_tiles, 0, s);
+    // Row (and column) starts are written only where a row begins and
+    // flagged in the mark bytes; the row fill completes the rest.
+    clear_marks(mark, P.n + 1, s);
     if (csc) {
-        fill<uint64_t>(csc, P.n, kNoRow, s);
+        clear_marks(cmark, P.n + 1, s);
         fill<uint64_t>(csc + P.n, 1, P.N, s);
+        fill<uint8_t>(cmark + P.n, 1, 1, s);
     }
     if (dups) fill<uint64_t>(dups, 1, 0, s);
     if (hist) fill<uint64_t>(hist, 32, 0, s);
-    fill<uint64_t>(row_ptr, P.n + 1, kNoRow, s);
-    if (rp_raw_ws) fill<uint64_t>(rp_raw_ws, P.n + 1, kNoRow, s);
 
     if (P.N > 0) {
         PrepArgs pa{P.E, P.N, src, dst, ghist, P.db, P.passes};
@@ -784,8 +824,8 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
             const int remaining = P.passes - 1 - p;  // passes after this one
             KeyT *out = (remaining % 2 == 0) ? keysA : keysB;
             KeyT *in = (remaining % 2 == 0) ? keysB : keysA;
-            PassArgs a{P.E, P.N, src, dst, in, out, status, gbase + p * kRadix, tickets + p, err, csc, P.db, 8 * p,
-                       (uint32_t)(p + 1)};
+            PassArgs a{P.E, P.N, src, dst, in, out, status, gbase + p * kRadix, tickets + p, err, csc, cmark, P.db,
+                       8 * p, (uint32_t)(p + 1)};
             const int g = (int)P.pass_tiles;
             if (csc && p == P.dpasses) {
                 { ProfScope _ps("radix_pass", s); radix_pass<IdT, KeyT, false, false, true><<<g, kPassThreads, 0, s>>>(a); }
@@ -798,8 +838,8 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
                 { ProfScope _ps("radix_pass", s); radix_pass<IdT, KeyT, false, false, false><<<g, kPassThreads, 0, s>>>(a); }
             }
         }
-        FinArgs fa{P.N, P.n, keysA, col, row_ptr, P.simple ? rp_raw_ws : nullptr, dups, fstatus, tickets + 15, err,
-                   P.db};
+        FinArgs fa{P.N, P.n, keysA, col, row_ptr, P.simple ? rp_raw_ws : nullptr, mark, dups, fstatus, tickets + 15,
+                   err, P.db};
         if (P.simple)
             { ProfScope _ps("csr_finish", s); csr_finish<IdT, KeyT, true><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa); }
         else
@@ -807,15 +847,16 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
     } else {
         fill<uint64_t>(row_ptr + P.n, 1, 0, s);
         if (rp_raw_ws) fill<uint64_t>(rp_raw_ws + P.n, 1, 0, s);
+        fill<uint8_t>(mark + P.n, 1, 1, s);
     }
-    row_fill(row_ptr, P.n + 1, cmin, P.chunks, s);
+    row_fill(row_ptr, mark, P.n + 1, cmin, P.chunks, s);
     if (hist) {
         const uint64_t *raw = row_ptr;
         if (rp_raw_ws) {
-            row_fill(rp_raw_ws, P.n + 1, cmin, P.chunks, s);
+            row_fill(rp_raw_ws, mark, P.n + 1, cmin, P.chunks, s);
             raw = rp_raw_ws;
         }
-        if (csc) row_fill(csc, P.n + 1, cmin, P.chunks, s);
+        if (csc) row_fill(csc, cmark, P.n + 1, cmin, P.chunks, s);
         { ProfScope _ps("degree_hist", s); degree_hist_kernel<<<fill_grid(P.n), 256, 0, s>>>(raw, csc, P.n, hist); }
     }
     return check_launch("edges_to_csr");

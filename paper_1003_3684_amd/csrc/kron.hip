@@ -93,8 +93,29 @@ template <int NT> __device__ __forceinline__ uint32_t bucket_of(uint32_t w, cons
     return b;
 }
 
+// Guide table over the top kGuideBits bits of a word: for every prefix the
+// (row, column) digits of the cell, unless a threshold falls inside the
+// prefix's range of words (kStraddle), where the word is compared against the
+// thresholds.  The bucket count is monotone in the word, so equal buckets at
+// both ends of a range make the entry exact for every word in it.
+constexpr int kGuideBits = 12;
+constexpr uint32_t kGuideSize = 1u << kGuideBits;
+constexpr uint32_t kStraddle = 0x100;
+
 template <typename IdT, typename AccT, bool POW2, int NT>
 __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__restrict__ src, IdT *__restrict__ dst) {
+    // With few thresholds the comparisons are cheaper than the table.
+    constexpr bool kGuide = NT > 3;
+    __shared__ uint16_t s_guide[kGuide ? kGuideSize : 1];
+    if (kGuide) {
+        for (uint32_t i = threadIdx.x; i < kGuideSize; i += kBlock) {
+            const uint32_t lo = i << (32 - kGuideBits), hi = lo | ((1u << (32 - kGuideBits)) - 1u);
+            const uint32_t blo = bucket_of<NT>(lo, a.tm1), bhi = bucket_of<NT>(hi, a.tm1);
+            const uint32_t rd = (uint32_t)(a.lut_row >> (4 * blo)) & 15u, cd = (uint32_t)(a.lut_col >> (4 * blo)) & 15u;
+            s_guide[i] = (uint16_t)(rd | (cd << 4) | (blo == bhi ? 0u : kStraddle));
+        }
+        __syncthreads();
+    }
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < a.num_edges; e += stride) {
         AccT u = 0, v = 0;
@@ -105,9 +126,16 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (blk * 4 + i < a.k) {
-                    const uint32_t b = bucket_of<NT>(ws[i], a.tm1);
-                    const AccT rd = (AccT)((a.lut_row >> (4 * b)) & 15u);
-                    const AccT cd = (AccT)((a.lut_col >> (4 * b)) & 15u);
+                    AccT rd, cd;
+                    const uint32_t ge = kGuide ? (uint32_t)s_guide[ws[i] >> (32 - kGuideBits)] : kStraddle;
+                    if (ge & kStraddle) {
+                        const uint32_t b = bucket_of<NT>(ws[i], a.tm1);
+                        rd = (AccT)((a.lut_row >> (4 * b)) & 15u);
+                        cd = (AccT)((a.lut_col >> (4 * b)) & 15u);
+                    } else {
+                        rd = (AccT)(ge & 15u);
+                        cd = (AccT)((ge >> 4) & 15u);
+                    }
                     if (POW2) {
                         u = (u << a.shift) | rd;
                         v = (v << a.shift) | cd;

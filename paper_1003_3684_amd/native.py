@@ -45,6 +45,8 @@ SIGNATURES = {
     "edges_to_csr": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "graph_stats_workspace_bytes": (_sz, [_u64, _u64, _i32]),
     "graph_stats": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _u64, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "path_stats_workspace_bytes": (_sz, [_u64]),
+    "path_stats": (_i32, [_u64, _vp, _vp, _i32, _vp, _u32, _vp, _vp, _sz, _vp]),
     "ensemble_workspace_bytes": (_sz, [_vp, _u32, _u64]),
     "ensemble_generate": (_i32, [_vp, _u32, _u32, _u64, _u64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "mlp_param_count": (_sz, [_vp]),
@@ -246,6 +248,26 @@ def graph_stats(n, src, dst, *, num_samples=10_000, seed=0, graph_id=0, ws=None,
 
 
 # ----------------------------------------------------------------------------- ensemble
+def path_stats_workspace_bytes(n):
+    return int(load().path_stats_workspace_bytes(n))
+
+
+def path_stats(n, row_ptr, col, sources, *, ws=None, out=None, stream=None):
+    """(sum of BFS distances, reachable pairs, largest distance) from `sources`
+    over a symmetric CSR; returns the device tensor of 3 u64 (as int64)."""
+    _require_cuda()
+    lib = load()
+    import numpy as np
+    srcs = np.ascontiguousarray(sources, np.int64)
+    if out is None:
+        out = torch.empty(3, dtype=torch.int64, device=row_ptr.device)
+    if ws is None:
+        ws = workspace(path_stats_workspace_bytes(n), row_ptr.device)
+    _check(lib.path_stats(n, _ptr(row_ptr), _ptr(col), col.element_size(), srcs.ctypes.data_as(_vp), srcs.size,
+                          _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
 def graph_descs(rows):
     """ctypes array of GraphDesc from dicts (kind 'pba' or 'kron')."""
     arr = (GraphDesc * len(rows))()
