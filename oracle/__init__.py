@@ -243,6 +243,19 @@ def path_stats(n, row_ptr, col, sources):
     return int(out[0]), int(out[1]), int(out[2])
 
 
+def block_matrix(n, src, dst, blocks):
+    """Coarse adjacency matrix (the adjacency-matrix view of the paper's
+    community figure, Results): counts[i][j] = number of edges (u, v) with
+    floor(u B / n) = i and floor(v B / n) = j, B = blocks."""
+    src = np.asarray(src, np.int64)
+    dst = np.asarray(dst, np.int64)
+    bi = (src * blocks) // n
+    bj = (dst * blocks) // n
+    counts = np.zeros((blocks, blocks), np.uint64)
+    np.add.at(counts, (bi, bj), 1)
+    return counts
+
+
 def graph_stats(n, src, dst, num_samples, seed, graph_id=0):
     """(degree histogram, gamma estimate, closed-wedge count) of one graph."""
     deg, hist = degree_histogram(n, src, dst)

@@ -542,3 +542,33 @@ def test_path_stats_match_scipy_bfs(orc):
         fin = np.isfinite(D) & (D > 0)
         want = (int(D[fin].sum()), int(fin.sum()), int(D[fin].max()) if fin.any() else 0)
         assert orc.path_stats(n, rp, col, srcs) == want
+
+
+# --------------------------------------------------------------------------- communities (block matrix)
+def test_block_matrix_of_kronecker_power_is_a_kronecker_power(orc):
+    # The deterministic Kronecker power of a 0/1 seed: coarsened to n0^l
+    # blocks, every nonzero cell of the l-th power of the seed holds the
+    # e0^(k-l) edges expanded from it -- the communities within communities.
+    from paper_1003_3684_amd import workloads as wl
+    seed = wl.FIG2_SEED
+    n0, e0, k = seed.shape[0], int(seed.sum()), 4
+    src, dst = orc.kron_enumerate(seed, k)
+    n = n0 ** k
+    power = np.ones((1, 1), np.int64)
+    for l in range(0, k + 1):
+        B = n0 ** l
+        got = orc.block_matrix(n, src, dst, B)
+        np.testing.assert_array_equal(got, power * e0 ** (k - l))
+        power = np.kron(power, seed.astype(np.int64))
+
+
+def test_block_matrix_uneven_blocks(orc):
+    # n = 10 vertices in B = 3 blocks: vertex v is in block floor(3 v / 10),
+    # so the blocks are {0..3}, {4..6}, {7..9}.
+    src = np.array([0, 3, 4, 6, 7, 9, 9], np.int64)
+    dst = np.array([9, 4, 3, 6, 0, 7, 9], np.int64)
+    want = np.array([[0, 1, 1],
+                     [1, 1, 0],
+                     [1, 0, 2]], np.uint64)
+    np.testing.assert_array_equal(orc.block_matrix(10, src, dst, 3), want)
+    assert orc.block_matrix(10, src, dst, 1)[0, 0] == 7
