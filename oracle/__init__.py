@@ -57,6 +57,8 @@ def _load():
         "orc_simple_csr": (C.c_int64, [C.c_uint64, C.c_uint64, i64p, i64p, u64p, i64p]),
         "orc_wedge_closed": (C.c_int64, [C.c_uint64, u64p, i64p, C.c_uint32, C.c_uint64, C.c_uint32]),
         "orc_path_stats": (None, [C.c_uint64, u64p, i64p, i64p, C.c_uint32, u64p, u64p, u64p]),
+        "orc_kron_xor_random": (C.c_int64, [C.c_uint32, u8p, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32,
+                                            u64p, i64p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -241,6 +243,21 @@ def path_stats(n, row_ptr, col, sources):
     out = np.zeros(3, np.uint64)
     _load().orc_path_stats(n, row_ptr, col, src, src.size, out[0:1], out[1:2], out[2:3])
     return int(out[0]), int(out[1]), int(out[2])
+
+
+def kron_xor_random(adj, k, num_random, seed, graph_id=0):
+    """CSR (row_ptr, col) of the deterministic Kronecker power XOR the random
+    graph of num_random uniform pair draws (PK section, randomization)."""
+    adj = np.ascontiguousarray(np.asarray(adj) != 0, np.uint8)
+    n0 = adj.shape[0]
+    e0 = int(adj.sum())
+    n = n0 ** k
+    row_ptr = np.zeros(n + 1, np.uint64)
+    col = np.zeros(max(e0 ** k + num_random, 1), np.int64)
+    m = _load().orc_kron_xor_random(n0, adj, k, num_random, seed, graph_id, row_ptr, col)
+    if m < 0:
+        raise MemoryError("oracle XOR graph")
+    return row_ptr, col[:m]
 
 
 def block_matrix(n, src, dst, blocks):

@@ -22,7 +22,7 @@
 
 typedef unsigned __int128 u128;
 
-enum { TAG_KRON = 1, TAG_PBA1 = 2, TAG_PBA2 = 3, TAG_WEDGE = 4 };
+enum { TAG_KRON = 1, TAG_PBA1 = 2, TAG_PBA2 = 3, TAG_WEDGE = 4, TAG_RANDOM = 6 };
 
 /* ---------------------------------------------------------------------------
  * Philox4x32-10 (SC'11 paper, section on Philox).  One round maps
@@ -590,4 +590,63 @@ void orc_path_stats(uint64_t n, const uint64_t *row_ptr, const int64_t *col, con
     *max_out = mx;
     free(dist);
     free(queue);
+}
+
+/* ------------------------------------------------------------------------
+ * Randomized PK by exclusive OR (PK section, randomization): the adjacency
+ * matrix of the deterministic Kronecker power XOR that of a random graph.
+ * The random graph is the set of distinct pairs among num_random uniform
+ * draws: draw i is Philox block (i, 0, 0, tag 6 | gid << 8), row =
+ * uidx(w0 + 2^32 w1, n), column = uidx(w2 + 2^32 w3, n).  A pair is an edge
+ * of the result when it is an edge of exactly one of the two graphs.
+ * Output: CSR of the result (rows ascending, columns ascending), returns the
+ * number of edges, or -1 on allocation failure.  row_ptr has n + 1 entries,
+ * col room for e0^k + num_random.
+ * ---------------------------------------------------------------------- */
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+int64_t orc_kron_xor_random(uint32_t n0, const uint8_t *adj, uint32_t k, uint64_t num_random, uint64_t seed,
+                            uint32_t gid, uint64_t *row_ptr, int64_t *col)
+{
+    uint32_t e0 = 0;
+    for (uint32_t c = 0; c < n0 * n0; ++c) e0 += adj[c] ? 1u : 0u;
+    uint64_t epk = 1, n = 1;
+    for (uint32_t l = 0; l < k; ++l) { epk *= e0; n *= n0; }
+    int64_t *ps = (int64_t *)malloc(sizeof(int64_t) * (epk ? epk : 1));
+    int64_t *pd = (int64_t *)malloc(sizeof(int64_t) * (epk ? epk : 1));
+    uint64_t *pk = (uint64_t *)malloc(sizeof(uint64_t) * (epk ? epk : 1));
+    uint64_t *rk = (uint64_t *)malloc(sizeof(uint64_t) * (num_random ? num_random : 1));
+    if (!ps || !pd || !pk || !rk) { free(ps); free(pd); free(pk); free(rk); return -1; }
+    orc_kron_enumerate(n0, adj, k, ps, pd, epk);
+    for (uint64_t e = 0; e < epk; ++e) pk[e] = (uint64_t)ps[e] * n + (uint64_t)pd[e];
+    for (uint64_t i = 0; i < num_random; ++i) {
+        uint32_t w[4];
+        draw(seed, i, 0, TAG_RANDOM, gid, w);
+        uint64_t a = orc_uidx((uint64_t)w[0] | ((uint64_t)w[1] << 32), n);
+        uint64_t b = orc_uidx((uint64_t)w[2] | ((uint64_t)w[3] << 32), n);
+        rk[i] = a * n + b;
+    }
+    qsort(pk, epk, sizeof(uint64_t), cmp_u64);
+    qsort(rk, num_random, sizeof(uint64_t), cmp_u64);
+    /* Merge the two sorted lists; the random list may repeat a pair. */
+    uint64_t i = 0, j = 0, out = 0;
+    for (uint64_t v = 0; v <= n; ++v) row_ptr[v] = 0;
+    while (i < epk || j < num_random) {
+        uint64_t key;
+        int in_pk = 0, in_rand = 0;
+        if (j >= num_random || (i < epk && pk[i] <= rk[j])) key = pk[i]; else key = rk[j];
+        while (i < epk && pk[i] == key) { in_pk = 1; ++i; }
+        while (j < num_random && rk[j] == key) { in_rand = 1; ++j; }
+        if (in_pk != in_rand) {
+            col[out++] = (int64_t)(key % n);
+            row_ptr[key / n + 1] += 1;
+        }
+    }
+    for (uint64_t v = 0; v < n; ++v) row_ptr[v + 1] += row_ptr[v];
+    free(ps); free(pd); free(pk); free(rk);
+    return (int64_t)out;
 }

@@ -572,3 +572,44 @@ def test_block_matrix_uneven_blocks(orc):
                      [1, 0, 2]], np.uint64)
     np.testing.assert_array_equal(orc.block_matrix(10, src, dst, 3), want)
     assert orc.block_matrix(10, src, dst, 1)[0, 0] == 7
+
+
+# --------------------------------------------------------------------------- randomized PK by XOR
+def _dense(n, rp, col):
+    A = np.zeros((n, n), np.uint8)
+    for u in range(n):
+        A[u, col[int(rp[u]):int(rp[u + 1])]] = 1
+    return A
+
+
+def test_kron_xor_random_brute_force(orc):
+    # Adjacency of the Kronecker power by numpy.kron, the random graph from
+    # the Philox primitive and the uidx map directly (uidx(U, R) =
+    # floor(U R / 2^64), checked here with Python integers), XOR elementwise.
+    seed_m = np.array([[1, 1, 0], [1, 0, 1], [0, 1, 1]], np.uint8)
+    k, M, seed, gid = 3, 400, 77, 5
+    n = 3 ** k
+    A = np.ones((1, 1), np.uint8)
+    for _ in range(k):
+        A = np.kron(A, seed_m)
+    R = np.zeros((n, n), np.uint8)
+    key = [seed & 0xFFFFFFFF, seed >> 32]
+    for i in range(M):
+        w = orc.philox([i & 0xFFFFFFFF, i >> 32, 0, 6 | (gid << 8)], key)
+        a = ((int(w[0]) | (int(w[1]) << 32)) * n) >> 64
+        b = ((int(w[2]) | (int(w[3]) << 32)) * n) >> 64
+        R[a, b] = 1
+    rp, col = orc.kron_xor_random(seed_m, k, M, seed, gid)
+    np.testing.assert_array_equal(_dense(n, rp, col), A ^ R)
+    # columns ascending within every row
+    for u in range(n):
+        c = col[int(rp[u]):int(rp[u + 1])]
+        assert np.all(np.diff(c) > 0)
+    assert len(col) == int(A.sum()) + int(R.sum()) - 2 * int((A & R).sum())
+
+
+def test_kron_xor_without_random_graph_is_the_power(orc):
+    from paper_1003_3684_amd import workloads as wl
+    rp, col = orc.kron_xor_random(wl.FIG2_SEED, 2, 0, 1)
+    A = np.kron(wl.FIG2_SEED, wl.FIG2_SEED)
+    np.testing.assert_array_equal(_dense(25, rp, col), A)
