@@ -59,6 +59,8 @@ def _load():
         "orc_path_stats": (None, [C.c_uint64, u64p, i64p, i64p, C.c_uint32, u64p, u64p, u64p]),
         "orc_kron_xor_random": (C.c_int64, [C.c_uint32, u8p, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32,
                                             u64p, i64p]),
+        "orc_kron_perturbed": (C.c_int64, [C.c_uint32, u8p, C.c_uint32, C.c_double, C.c_double, C.c_uint64,
+                                           C.c_uint32, i64p, i64p, C.c_uint64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -258,6 +260,21 @@ def kron_xor_random(adj, k, num_random, seed, graph_id=0):
     if m < 0:
         raise MemoryError("oracle XOR graph")
     return row_ptr, col[:m]
+
+
+def kron_perturbed(adj, k, p_add, p_del, seed, graph_id=0, cap=None):
+    """Kronecker power with the seed temporarily modified at every expansion
+    (PK section, randomization); (src, dst) in stack order."""
+    adj = np.ascontiguousarray(np.asarray(adj) != 0, np.uint8)
+    n0 = adj.shape[0]
+    if cap is None:
+        cap = (n0 * n0) ** k
+    src = np.zeros(max(cap, 1), np.int64)
+    dst = np.zeros(max(cap, 1), np.int64)
+    m = _load().orc_kron_perturbed(n0, adj, k, p_add, p_del, seed, graph_id, src, dst, cap)
+    if m < 0:
+        raise ValueError("more than cap edges")
+    return src[:m], dst[:m]
 
 
 def block_matrix(n, src, dst, blocks):

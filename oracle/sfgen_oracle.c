@@ -22,7 +22,7 @@
 
 typedef unsigned __int128 u128;
 
-enum { TAG_KRON = 1, TAG_PBA1 = 2, TAG_PBA2 = 3, TAG_WEDGE = 4, TAG_RANDOM = 6 };
+enum { TAG_KRON = 1, TAG_PBA1 = 2, TAG_PBA2 = 3, TAG_WEDGE = 4, TAG_RANDOM = 6, TAG_PERTURB = 7 };
 
 /* ---------------------------------------------------------------------------
  * Philox4x32-10 (SC'11 paper, section on Philox).  One round maps
@@ -649,4 +649,60 @@ int64_t orc_kron_xor_random(uint32_t n0, const uint8_t *adj, uint32_t k, uint64_
     for (uint64_t v = 0; v < n; ++v) row_ptr[v + 1] += row_ptr[v];
     free(ps); free(pd); free(pk); free(rk);
     return (int64_t)out;
+}
+
+/* ------------------------------------------------------------------------
+ * Randomized PK by temporary seed modification (PK section, randomization):
+ * the meta-edge stack of orc_kron_enumerate, except that every meta-edge of
+ * iteration i < k is replaced by the edges of a perturbed copy of the seed:
+ * an absent cell c is added with probability p_add, a present one deleted
+ * with probability p_del.  The draws of meta-edge (i, row, col) come from
+ * Philox blocks (row, col, i | b << 8, tag 7 | gid << 8), b = c / 4, word
+ * c mod 4, compared with floor(p 2^32).  The seed's own edges (iteration 1)
+ * are not perturbed.  Emits edges in stack order; returns their number, or
+ * -1 when more than cap would be written.
+ * ---------------------------------------------------------------------- */
+int64_t orc_kron_perturbed(uint32_t n0, const uint8_t *adj, uint32_t k, double p_add, double p_del, uint64_t seed,
+                           uint32_t gid, int64_t *src, int64_t *dst, uint64_t cap)
+{
+    const uint32_t C = n0 * n0;
+    const uint64_t thr_add = orc_bernoulli_threshold(p_add), thr_del = orc_bernoulli_threshold(p_del);
+    size_t stack_cap = (size_t)C * (k + 1) + 1;
+    meta_edge *stack = (meta_edge *)malloc(sizeof(meta_edge) * stack_cap);
+    uint8_t *cell = (uint8_t *)malloc(C ? C : 1);
+    if (!stack || !cell) { free(stack); free(cell); return -1; }
+    size_t top = 0;
+    for (int64_t c = (int64_t)C - 1; c >= 0; --c)
+        if (adj[c]) {
+            meta_edge me = {1, c / n0, c % n0};
+            stack[top++] = me;
+        }
+    int64_t emitted = 0;
+    while (top > 0) {
+        meta_edge me = stack[--top];
+        if (me.iter == k) {
+            if ((uint64_t)emitted >= cap) { free(stack); free(cell); return -1; }
+            src[emitted] = me.row;
+            dst[emitted] = me.col;
+            ++emitted;
+            continue;
+        }
+        /* the temporarily modified seed of this meta-edge */
+        for (uint32_t c = 0; c < C; ++c) {
+            uint32_t w[4];
+            uint32_t ctr[4] = {(uint32_t)me.row, (uint32_t)me.col, me.iter | ((c / 4) << 8), TAG_PERTURB | (gid << 8)};
+            uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+            orc_philox4x32_10(ctr, key, w);
+            uint64_t x = w[c % 4];
+            cell[c] = adj[c] ? (x < thr_del ? 0 : 1) : (x < thr_add ? 1 : 0);
+        }
+        for (int64_t c = (int64_t)C - 1; c >= 0; --c)
+            if (cell[c]) {
+                meta_edge ch = {me.iter + 1, me.row * n0 + c / n0, me.col * n0 + c % n0};
+                stack[top++] = ch;
+            }
+    }
+    free(stack);
+    free(cell);
+    return emitted;
 }

@@ -613,3 +613,54 @@ def test_kron_xor_without_random_graph_is_the_power(orc):
     rp, col = orc.kron_xor_random(wl.FIG2_SEED, 2, 0, 1)
     A = np.kron(wl.FIG2_SEED, wl.FIG2_SEED)
     np.testing.assert_array_equal(_dense(25, rp, col), A)
+
+
+# --------------------------------------------------------------------------- randomized PK by seed modification
+def test_perturbed_without_changes_is_the_power(orc):
+    from paper_1003_3684_amd import workloads as wl
+    s0, d0 = orc.kron_enumerate(wl.FIG2_SEED, 4)
+    s1, d1 = orc.kron_perturbed(wl.FIG2_SEED, 4, 0.0, 0.0, 5)
+    np.testing.assert_array_equal(s0, s1)
+    np.testing.assert_array_equal(d0, d1)
+
+
+def test_perturbed_extremes_are_kronecker_products(orc):
+    # p_add = p_del = 1 flips every cell at every expansion: the graph is
+    # seed (x) complement (x) ... (x) complement.  p_del = 1, p_add = 0
+    # deletes everything below the first iteration.
+    seed_m = np.array([[1, 1, 0], [0, 1, 1], [1, 0, 0]], np.uint8)
+    k = 4
+    comp = 1 - seed_m
+    A = seed_m.astype(np.int64)
+    for _ in range(k - 1):
+        A = np.kron(A, comp)
+    s, d = orc.kron_perturbed(seed_m, k, 1.0, 1.0, 9)
+    n = 3 ** k
+    got = np.zeros((n, n), np.int64)
+    got[s, d] += 1
+    np.testing.assert_array_equal(got, A)
+    s, d = orc.kron_perturbed(seed_m, k, 0.0, 1.0, 9)
+    assert s.size == 0
+    s, d = orc.kron_perturbed(seed_m, 1, 0.7, 0.7, 9)  # one level: the seed itself
+    assert s.size == int(seed_m.sum())
+
+
+def test_perturbed_subset_and_expected_size(orc):
+    from paper_1003_3684_amd import workloads as wl
+    seed_m = wl.FIG2_SEED
+    n0, e0, k = 5, 11, 5
+    n = n0 ** k
+    base = set(zip(*orc.kron_enumerate(seed_m, k)))
+    # additions only: a superset of the power; deletions only: a subset
+    up = set(zip(*orc.kron_perturbed(seed_m, k, 0.02, 0.0, 3)))
+    down = set(zip(*orc.kron_perturbed(seed_m, k, 0.0, 0.1, 3)))
+    assert base < up and down < base
+    # every meta-edge expands independently: E|G_k| = e0 f^(k-1) with
+    # f = e0 (1 - p_del) + (n0^2 - e0) p_add
+    p_add, p_del = 0.05, 0.1
+    f = e0 * (1 - p_del) + (n0 * n0 - e0) * p_add
+    sizes = [orc.kron_perturbed(seed_m, k, p_add, p_del, s)[0].size for s in range(24)]
+    assert abs(np.mean(sizes) / (e0 * f ** (k - 1)) - 1) < 0.04
+    # distinct meta-edges give distinct edges
+    s, d = orc.kron_perturbed(seed_m, k, p_add, p_del, 1)
+    assert np.unique(s * n + d).size == s.size
