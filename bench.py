@@ -231,7 +231,19 @@ def _bench_pba(sfg, wl, torch, reps=3):
     gen_ms, csr_ms = a.elapsed_time(b) / reps, b.elapsed_time(d) / reps
     out = {"workload": c["name"], "edges": E, "gen_ms": gen_ms, "gen_edges_per_s": E / (gen_ms / 1e3),
            "csr_ms": csr_ms, "step_edges_per_s": E / ((gen_ms + csr_ms) / 1e3)}
-    del src, dst, ws, rp, col
+    # Table 2 analogue: average path length and diameter estimate from 64
+    # sampled sources, on the symmetrized graph.
+    import numpy as np
+    del ws
+    torch.cuda.empty_cache()
+    sources = np.random.default_rng(c["seed"]).integers(0, c["n"], 64)
+    pws = sfg.workspace(sfg.path_stats_workspace_bytes(c["n"]))
+    t0 = time.perf_counter()
+    res = sfg.path_stats(c["n"], rp, col, sources, ws=pws).cpu().numpy()
+    path_s = time.perf_counter() - t0
+    out["paths"] = {"sources": 64, "avg_path_length": float(res[0]) / max(int(res[1]), 1),
+                    "diameter_estimate": int(res[2]), "seconds": path_s}
+    del src, dst, rp, col, pws
     torch.cuda.empty_cache()
     return out
 

@@ -79,7 +79,8 @@ int sfg_device_error(void *stream, uint32_t *code);
  * milliseconds; sfg_profile_reset forgets all records.  Kernel names:
  * "kron_sample", "kron_enumerate", "csr_prepare", "radix_pass",
  * "csr_finish", "csr_rowfill", "degree_hist", "pba_draw1", "pba_resolve",
- * "pba_count", "pba_scan", "pba_draw2", "pba_substitute", "path_level". */
+ * "pba_count", "pba_scan", "pba_draw2", "pba_substitute", "path_level",
+ * "block_count", "random_pairs", "perturb_expand". */
 int sfg_profile_enable(int on);
 int sfg_profile_reset(void);
 int sfg_profile_query(const char *name, uint64_t *launches, double *total_ms);
@@ -240,6 +241,81 @@ int graph_stats(uint64_t n, uint64_t num_edges, const void *src, const void *dst
 size_t path_stats_workspace_bytes(uint64_t n);
 int path_stats(uint64_t n, const uint64_t *row_ptr, const void *col, int id_bytes, const int64_t *sources,
                uint32_t num_sources, uint64_t *out, void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * kron_perturbed -- randomized PK by temporary seed modification (PK section,
+ * randomization: meta-edges added or deleted in the replacement phase of
+ * every iteration by modifying the seed graph temporarily).
+ *
+ * The expansion of enumerate mode (nonzero entries of seed_matrix are the
+ * seed's edges, iteration 1 is the seed itself), except that each meta-edge
+ * (iteration i < k, row, col) is replaced by the edges of its own copy of the
+ * seed in which an absent cell c is added with probability p_add and a
+ * present cell deleted with probability p_del: word c mod 4 of Philox block
+ * (row, col, i | (c / 4) << 8, tag 7 | graph_id << 8), compared as u64 with
+ * floor(p 2^32).  Edges come out in the paper's meta-edge stack order (cell
+ * order within every expansion, recursively); with p_add = p_del = 0 this is
+ * kron_generate's enumerate mode entry for entry.
+ *
+ * n0 <= 8, n0^k <= 2^32.  capacity bounds the edges of every iteration (the
+ * output arrays and the workspace are sized by it); an iteration above it
+ * fails with ENOSPACE.  *num_edges (device u64) receives the edge count.
+ * The call waits for the stream after every iteration (the next size comes
+ * from the device).
+ * workspace: device, kron_perturbed_workspace_bytes(capacity) (32 B per edge).
+ * Errors: EINVAL (n0 outside [2, 8], k == 0, probabilities outside [0, 1],
+ * bad seed entry or no edge, bad id_bytes, graph_id >= 2^24, NULL buffers);
+ * ERANGE (n0^k > 2^32, k > 255, ids beyond int32 with id_bytes 4); ENOSPACE.
+ * ---------------------------------------------------------------------- */
+size_t kron_perturbed_workspace_bytes(uint64_t capacity);
+int kron_perturbed(uint32_t n0, const float *seed_matrix, uint32_t k, double p_add, double p_del, uint64_t seed,
+                   uint32_t graph_id, int id_bytes, uint64_t capacity, void *src, void *dst, uint64_t *num_edges,
+                   void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * kron_xor_random -- randomized PK (PK section, randomization): the
+ * adjacency matrix of the deterministic Kronecker power XOR that of a random
+ * graph.
+ *
+ * The Kronecker power is kron_generate's enumerate mode on the 0/1 seed
+ * (nonzero entries of seed_matrix are its edges): e0^k distinct pairs over
+ * n = n0^k vertices.  The random graph is the set of distinct pairs among
+ * num_random draws; draw i is Philox block (i, 0, 0, tag 6 | graph_id << 8),
+ * row = uidx(w0 + 2^32 w1, n), column = uidx(w2 + 2^32 w3, n).  The result
+ * holds every pair that is an edge of exactly one of the two graphs, as CSR
+ * with columns ascending within each row; row_ptr[n] is its edge count.
+ *
+ * seed_matrix: host, n0 * n0 float32 (only zero / nonzero matters), n0 <= 64.
+ * row_ptr:     device, n + 1 u64.
+ * col:         device, room for e0^k + num_random ids (id_bytes wide).
+ * workspace:   device, kron_xor_random_workspace_bytes(...).
+ * Errors: EINVAL (n0 outside [2, 64], k == 0, a negative / NaN / infinite
+ * entry, no edge in the seed, bad id_bytes, NULL buffers, graph_id >= 2^24);
+ * ERANGE (n0^k > 2^31, e0^k or num_random > 2^40, ids beyond int32 with
+ * id_bytes 4); ENOSPACE.  kron_xor_random_workspace_bytes returns 0 for
+ * arguments that would be rejected.
+ * ---------------------------------------------------------------------- */
+size_t kron_xor_random_workspace_bytes(uint32_t n0, const float *seed_matrix, uint32_t k, uint64_t num_random,
+                                       int id_bytes);
+int kron_xor_random(uint32_t n0, const float *seed_matrix, uint32_t k, uint64_t num_random, uint64_t seed,
+                    uint32_t graph_id, int id_bytes, uint64_t *row_ptr, void *col, void *workspace,
+                    size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * block_matrix -- the coarse adjacency matrix of an edge list, the view in
+ * which the paper shows community structure (Results, community figure:
+ * blocks in PBA graphs, communities within communities in Kronecker graphs).
+ *
+ * counts[i * blocks + j] = number of edges (u, v) with floor(u blocks / n) = i
+ * and floor(v blocks / n) = j.  Edges with an endpoint outside [0, n) are not
+ * counted.
+ * src, dst: device, num_edges ids each (id_bytes wide).
+ * counts:   device, blocks * blocks u64, overwritten.
+ * Errors: EINVAL (n == 0, bad id_bytes, blocks == 0, blocks > 4096,
+ * blocks > n, NULL buffers); ERANGE (n > 2^48).
+ * ---------------------------------------------------------------------- */
+int block_matrix(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes, uint32_t blocks,
+                 uint64_t *counts, void *stream);
 
 /* ------------------------------------------------------------------------
  * ensemble_generate -- a batched ensemble of graphs (PBA and Kronecker

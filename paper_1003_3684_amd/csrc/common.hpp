@@ -35,6 +35,13 @@ int csr_build(uint64_t n, uint64_t num_edges, const void *src, const void *dst, 
               uint64_t *row_ptr, void *col, uint64_t *degree_hist32, uint64_t *num_duplicates, void *workspace,
               size_t workspace_bytes, hipStream_t s, const uint64_t **raw_rows);
 
+// CSR of the symmetric difference of two edge sets: entries [0, split) are the
+// first graph (distinct pairs), entries [split, num_entries) the second (pairs
+// may repeat); a pair is kept once when it is in exactly one of them.
+size_t csr_xor_workspace_bytes(uint64_t n, uint64_t num_entries);
+int csr_xor_build(uint64_t n, uint64_t num_entries, uint64_t split, const void *src, const void *dst, int id_bytes,
+                  uint64_t *row_ptr, void *col, void *workspace, size_t workspace_bytes, hipStream_t s);
+
 // Counter-word tags of the Philox streams.
 enum : uint32_t { TAG_KRON = 1, TAG_PBA1 = 2, TAG_PBA2 = 3, TAG_WEDGE = 4 };
 

@@ -99,12 +99,23 @@ __device__ __forceinline__ KeyT entry_key(const IdT *src, const IdT *dst, uint64
     return pack<IdT, KeyT>(dst[j], src[j], wb);
 }
 
+// Key of entry idx with tb origin bits below it: entries at or after `split`
+// come from the second graph (origin 1).
+template <typename IdT, typename KeyT, bool SYM>
+__device__ __forceinline__ KeyT tagged_key(const IdT *src, const IdT *dst, uint64_t E, uint64_t idx, int wb, int tb,
+                                           uint64_t split) {
+    const KeyT k = entry_key<IdT, KeyT, SYM>(src, dst, E, idx, wb);
+    return tb ? (KeyT)((k << 1) | (KeyT)(idx >= split ? 1u : 0u)) : k;
+}
+
 // --------------------------------------------------------------------------- prepare
 struct PrepArgs {
     uint64_t E, N;
     const void *src, *dst;
     uint64_t *ghist;   // [passes][256]
     int wb, passes;    // wb: width of the destination field
+    int tb;            // origin bits below the entry (XOR mode)
+    uint64_t split;    // first entry of origin 1
 };
 
 template <typename IdT, typename KeyT, bool SYM>
@@ -125,7 +136,7 @@ __global__ __launch_bounds__(256) void csr_prepare(PrepArgs a) {
 #pragma unroll
         for (int u = 0; u < kPrepUnroll; ++u) {
             const uint64_t i = i0 + (uint64_t)u * 256;
-            k[u] = i < a.N ? entry_key<IdT, KeyT, SYM>(src, dst, a.E, i, a.wb) : (KeyT)0;
+            k[u] = i < a.N ? tagged_key<IdT, KeyT, SYM>(src, dst, a.E, i, a.wb, a.tb, a.split) : (KeyT)0;
         }
 #pragma unroll
         for (int u = 0; u < kPrepUnroll; ++u) {
@@ -166,12 +177,15 @@ struct PassArgs {
     void *out;
     uint64_t *status;       // [tiles][256]
     const uint64_t *gbase;  // [256] of this pass
+    const uint64_t *ghist;  // [256] of this pass: digits no entry has skip the look-back
     uint32_t *ticket;
     uint32_t *err;
     uint64_t *csc;          // column starts (BOUND passes only)
     uint8_t *cmark;         // 1 where a column start was written (BOUND passes only)
     int wb, shift;          // wb: width of the destination field
     uint32_t tag;
+    int tb;                 // origin bits below the entry (first pass, XOR mode)
+    uint64_t split;         // first entry of origin 1
 };
 
 // BOUND: the input keys are ordered by destination; mark the first position
@@ -215,8 +229,8 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
         const uint64_t idx = wbase + (uint64_t)i * 64 + lane;
         const bool valid = full || idx < a.N;
         if (FIRST)
-            k[i] = valid ? entry_key<IdT, KeyT, SYM>(static_cast<const IdT *>(a.src), static_cast<const IdT *>(a.dst),
-                                                      a.E, idx, a.wb)
+            k[i] = valid ? tagged_key<IdT, KeyT, SYM>(static_cast<const IdT *>(a.src), static_cast<const IdT *>(a.dst),
+                                                       a.E, idx, a.wb, a.tb, a.split)
                          : (KeyT)0;
         else
             k[i] = valid ? static_cast<const KeyT *>(a.in)[idx] : (KeyT)0;
@@ -292,9 +306,15 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
     // trip covers kLanesPerDigit kLookWindow earlier tiles.  Lane 0 of the
     // group publishes: the tile's own count first, its inclusive prefix once
     // known.
+    // A digit that no entry of the pass has (known from the histogram pass)
+    // has a zero prefix everywhere: its lanes neither publish nor walk.  Key
+    // ranges that leave digit values unused (ids below a power of the radix,
+    // generators with zero cells) save that part of the status traffic.
     const uint32_t dg = (uint32_t)tid / kLanesPerDigit, part = (uint32_t)tid % kLanesPerDigit;
     const uint64_t my_cnt = s_tot[dg];
-    if (part == 0) store_agent(a.status + tile * kRadix + dg, status_word(a.tag, tile == 0 ? kFlagIncl : kFlagAgg, my_cnt));
+    const bool used = a.ghist[dg] != 0;
+    if (part == 0 && used)
+        store_agent(a.status + tile * kRadix + dg, status_word(a.tag, tile == 0 ? kFlagIncl : kFlagAgg, my_cnt));
 
     uint64_t tot;
     const uint64_t ex = block_exclusive_scan_256(cnt, s_tmp, &tot);
@@ -308,7 +328,7 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
         if (d[i] < kRadix) s_keys[s_off[d[i]] + s_cnt[w][d[i]] + r[i]] = k[i];
 
     uint64_t prefix = 0;
-    if (tile > 0) {
+    if (tile > 0 && used) {
         uint64_t j = tile;  // tiles below j are still to be examined
         for (;;) {
             // This lane's predecessors: j - 1 - (part kLookWindow + i).  One
@@ -436,27 +456,34 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish_plain(FinArgs a) {
     }
 }
 
-template <typename IdT, typename KeyT, bool SIMPLE>
+// Compacting finish.  SIMPLE (XOR = false): keep the first of every run of
+// equal entries unless it is a self-loop.  XOR: the keys carry an origin bit
+// below the entry (0 = first graph, whose entries are distinct; 1 = second
+// graph, whose entries may repeat), so the first graph's copy of a pair sorts
+// first; keep one copy of a pair present in exactly one of the two graphs.
+// Output positions come from a look-back scan of the kept counts.
+template <typename IdT, typename KeyT, bool XOR>
 __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
+    constexpr int TB = XOR ? 1 : 0;  // origin bits below the entry
     // Blocked reads (16 consecutive keys per thread) would hit one LDS bank
-    // for the whole wave; one pad slot per 16 keys spreads them.
+    // for the whole wave; one pad slot per 16 keys spreads them.  Slot 0 holds
+    // the key before the tile, the last slot the key after it.
     __shared__ KeyT s_keys[kFinTile + kFinTile / 16 + 2];
     __shared__ uint64_t s_tmp[4];
     __shared__ uint64_t s_base;
-    __shared__ uint32_t s_tile;
     __shared__ uint32_t s_dups[kFinThreads / 64];
     const int tid = threadIdx.x;
-    if (tid == 0) s_tile = blockIdx.x;  // dispatch order (see radix_pass)
-    __syncthreads();
-    const uint64_t tile = s_tile;
+    const uint64_t tile = blockIdx.x;  // dispatch order (see radix_pass)
     const uint64_t t0 = tile * kFinTile;
     const KeyT *K = static_cast<const KeyT *>(a.keys);
-    // Striped (coalesced) load into LDS; slot 0 holds the key before the tile.
     for (int i = tid; i < kFinTile; i += kFinThreads) {
         const uint64_t idx = t0 + i;
         s_keys[fin_slot(i + 1)] = idx < a.N ? K[idx] : (KeyT)0;
     }
-    if (tid == 0) s_keys[0] = t0 > 0 ? K[t0 - 1] : (KeyT)0;
+    if (tid == 0) {
+        s_keys[0] = t0 > 0 ? K[t0 - 1] : (KeyT)0;
+        s_keys[fin_slot(kFinTile + 1)] = t0 + kFinTile < a.N ? K[t0 + kFinTile] : (KeyT)0;
+    }
     __syncthreads();
     const KeyT mask = ((KeyT)1 << a.wb) - 1;
     // Blocked view: thread t owns positions t*16 .. t*16+15 of the tile.
@@ -467,76 +494,68 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
         const uint64_t idx = t0 + p;
         if (idx < a.N) {
             const KeyT key = s_keys[fin_slot(p + 1)], prev = s_keys[fin_slot(p)];
-            const bool dup = idx > 0 && key == prev;
-            ndup += dup;
-            const bool keep = !SIMPLE || (!dup && (key >> a.wb) != (key & mask));
+            bool keep;
+            if (XOR) {
+                const KeyT pair = key >> TB, next = s_keys[fin_slot(p + 2)];
+                const bool first = idx == 0 || (prev >> TB) != pair;
+                const bool alone = (key & 1) != 0 || idx + 1 >= a.N || (next >> TB) != pair;
+                keep = first && alone;
+            } else {
+                const bool dup = idx > 0 && key == prev;
+                ndup += dup;
+                keep = !dup && (key >> a.wb) != (key & mask);
+            }
             keep_bits |= (uint32_t)keep << j;
             nkeep += keep;
         }
     }
-    uint64_t cbase = t0;  // output position of this tile's first kept entry
-    if (SIMPLE) {
-        // Exclusive scan of kept counts over the threads, then over tiles.
-        uint64_t tot;
-        const uint64_t lane_pre = 0;
-        (void)lane_pre;
-        const uint64_t ex = block_exclusive_scan_256(nkeep, s_tmp, &tot);
-        if (tid == 0) {
-            uint64_t *st = a.status + tile;
-            uint64_t prefix = 0;
-            if (tile == 0) {
-                store_agent(st, status_word(1, kFlagIncl, tot));
-            } else {
-                store_agent(st, status_word(1, kFlagAgg, tot));
-                uint64_t j = tile - 1;
-                for (;;) {
-                    uint64_t v = load_agent(a.status + j);
-                    uint32_t spins = 0;
-                    while ((uint32_t)(v >> 58) != 1u) {
-                        if (++spins > kSpinLimit || ((spins & 1023) == 0 && load_agent(a.err) != 0)) {
-                            raise_device_error(a.err, DEVERR_LOOKBACK);
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(1);
-                        v = load_agent(a.status + j);
+    // Exclusive scan of kept counts over the threads, then over tiles.
+    uint64_t tot;
+    const uint64_t ex = block_exclusive_scan_256(nkeep, s_tmp, &tot);
+    if (tid == 0) {
+        uint64_t *st = a.status + tile;
+        uint64_t prefix = 0;
+        if (tile == 0) {
+            store_agent(st, status_word(1, kFlagIncl, tot));
+        } else {
+            store_agent(st, status_word(1, kFlagAgg, tot));
+            uint64_t j = tile - 1;
+            for (;;) {
+                uint64_t v = load_agent(a.status + j);
+                uint32_t spins = 0;
+                while ((uint32_t)(v >> 58) != 1u) {
+                    if (++spins > kSpinLimit || ((spins & 1023) == 0 && load_agent(a.err) != 0)) {
+                        raise_device_error(a.err, DEVERR_LOOKBACK);
+                        break;
                     }
-                    prefix += v & ((1ull << 56) - 1);
-                    if (((v >> 56) & 3) == kFlagIncl || (uint32_t)(v >> 58) != 1u || j == 0) break;
-                    --j;
+                    __builtin_amdgcn_s_sleep(1);
+                    v = load_agent(a.status + j);
                 }
-                store_agent(st, status_word(1, kFlagIncl, prefix + tot));
+                prefix += v & ((1ull << 56) - 1);
+                if (((v >> 56) & 3) == kFlagIncl || (uint32_t)(v >> 58) != 1u || j == 0) break;
+                --j;
             }
-            s_base = prefix;
+            store_agent(st, status_word(1, kFlagIncl, prefix + tot));
         }
-        __syncthreads();
-        cbase = s_base + ex;
+        s_base = prefix;
     }
+    __syncthreads();
+    const uint64_t cbase = s_base + ex;
     IdT *col = static_cast<IdT *>(a.col);
-    uint64_t c = SIMPLE ? cbase : t0 + (uint64_t)tid * kFinItems;
+    uint64_t c = cbase;
 #pragma unroll
     for (int j = 0; j < kFinItems; ++j) {
         const int p = tid * kFinItems + j;
         const uint64_t idx = t0 + p;
         if (idx < a.N) {
-            const KeyT key = s_keys[fin_slot(p + 1)], prev = s_keys[fin_slot(p)];
+            const KeyT key = s_keys[fin_slot(p + 1)] >> TB, prev = s_keys[fin_slot(p)] >> TB;
             const uint64_t row = (uint64_t)(key >> a.wb);
             if (idx == 0 || row != (uint64_t)(prev >> a.wb)) {
                 a.rp[row] = c;
                 if (a.rp_raw) a.rp_raw[row] = idx;
                 a.mark[row] = 1;
             }
-            if (SIMPLE) {
-                if ((keep_bits >> j) & 1u) col[c++] = (IdT)(key & mask);
-            } else {
-                ++c;
-            }
-        }
-    }
-    if (!SIMPLE) {
-        // Columns, striped for coalesced stores.
-        for (int i = tid; i < kFinTile; i += kFinThreads) {
-            const uint64_t idx = t0 + i;
-            if (idx < a.N) col[idx] = (IdT)(s_keys[fin_slot(i + 1)] & mask);
+            if ((keep_bits >> j) & 1u) col[c++] = (IdT)(key & mask);
         }
     }
     if (a.dups) {
@@ -550,16 +569,11 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
             if (t) atomicAdd((unsigned long long *)a.dups, (unsigned long long)t);
         }
     }
-    // The last tile closes row n.
+    // The last tile closes row n: total kept = base of this tile + its kept.
     if (t0 + kFinTile >= a.N && tid == kFinThreads - 1) {
-        if (SIMPLE) {
-            // total kept = base of this tile + kept in this tile
-            uint64_t tail = cbase;
-            for (int j = 0; j < kFinItems; ++j) tail += (keep_bits >> j) & 1u;
-            a.rp[a.n] = tail;
-        } else {
-            a.rp[a.n] = a.N;
-        }
+        uint64_t tail = cbase;
+        for (int j = 0; j < kFinItems; ++j) tail += (keep_bits >> j) & 1u;
+        a.rp[a.n] = tail;
         if (a.rp_raw) a.rp_raw[a.n] = a.N;
         a.mark[a.n] = 1;
     }
@@ -699,20 +713,26 @@ int bits_for(uint64_t n) {  // bits to hold ids in [0, n)
 struct Plan {
     uint64_t n, E, N;
     int wb, db, kb, passes, key_bytes, dpasses;
-    bool sym, simple, hist, directed_hist;
+    bool sym, simple, hist, directed_hist, xor_mode;
+    int tb;
+    uint64_t split;
     uint64_t pass_tiles, fin_tiles, chunks;
     // workspace carving
     size_t off_keysA, off_keysB, off_status, off_ghist, off_gbase, off_tickets, off_indeg, off_rpraw, off_mark,
         off_cmark, off_cmin, off_fstatus, total;
 };
 
-Plan make_plan(uint64_t n, uint64_t E, int id_bytes, uint32_t flags, bool want_hist) {
+Plan make_plan(uint64_t n, uint64_t E, int id_bytes, uint32_t flags, bool want_hist, bool xor_mode = false,
+               uint64_t split = 0) {
     Plan p;
     memset(&p, 0, sizeof(p));
     p.n = n;
     p.E = E;
     p.sym = flags & SFG_CSR_SYMMETRIZE;
-    p.simple = flags & SFG_CSR_SIMPLE;
+    p.simple = (flags & SFG_CSR_SIMPLE) || xor_mode;
+    p.xor_mode = xor_mode;
+    p.tb = xor_mode ? 1 : 0;
+    p.split = split;
     p.N = p.sym ? 2 * E : E;
     p.wb = bits_for(n);
     p.hist = want_hist;
@@ -721,7 +741,7 @@ Plan make_plan(uint64_t n, uint64_t E, int id_bytes, uint32_t flags, bool want_h
     // that some pass boundary leaves the keys ordered by destination.
     p.db = p.directed_hist ? 8 * ((p.wb + 7) / 8) : p.wb;
     p.dpasses = p.db / 8;
-    p.kb = p.wb + p.db;
+    p.kb = p.wb + p.db + p.tb;
     p.passes = (p.kb + 7) / 8;
     p.key_bytes = p.kb <= 32 ? 4 : 8;
     p.pass_tiles = (p.N + kPassTile - 1) / kPassTile;
@@ -809,7 +829,7 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
     if (hist) fill<uint64_t>(hist, 32, 0, s);
 
     if (P.N > 0) {
-        PrepArgs pa{P.E, P.N, src, dst, ghist, P.db, P.passes};
+        PrepArgs pa{P.E, P.N, src, dst, ghist, P.db, P.passes, P.tb, P.split};
         // Every histogram workgroup stays resident (32 KB of LDS each).
         const int pg = (int)std::max<uint64_t>(1, std::min<uint64_t>((P.N + 255) / 256,
                                                                       (uint64_t)device_cu_count() * kPrepBlocksPerCu));
@@ -824,8 +844,8 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
             const int remaining = P.passes - 1 - p;  // passes after this one
             KeyT *out = (remaining % 2 == 0) ? keysA : keysB;
             KeyT *in = (remaining % 2 == 0) ? keysB : keysA;
-            PassArgs a{P.E, P.N, src, dst, in, out, status, gbase + p * kRadix, tickets + p, err, csc, cmark, P.db,
-                       8 * p, (uint32_t)(p + 1)};
+            PassArgs a{P.E, P.N, src, dst, in, out, status, gbase + p * kRadix, ghist + p * kRadix, tickets + p, err,
+                       csc, cmark, P.db, 8 * p, (uint32_t)(p + 1), P.tb, P.split};
             const int g = (int)P.pass_tiles;
             if (csc && p == P.dpasses) {
                 { ProfScope _ps("radix_pass", s); radix_pass<IdT, KeyT, false, false, true><<<g, kPassThreads, 0, s>>>(a); }
@@ -840,8 +860,10 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
         }
         FinArgs fa{P.N, P.n, keysA, col, row_ptr, P.simple ? rp_raw_ws : nullptr, mark, dups, fstatus, tickets + 15,
                    err, P.db};
-        if (P.simple)
+        if (P.xor_mode)
             { ProfScope _ps("csr_finish", s); csr_finish<IdT, KeyT, true><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa); }
+        else if (P.simple)
+            { ProfScope _ps("csr_finish", s); csr_finish<IdT, KeyT, false><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa); }
         else
             { ProfScope _ps("csr_finish", s); csr_finish_plain<IdT, KeyT><<<fill_grid(P.N), kFinThreads, 0, s>>>(fa); }
     } else {
@@ -906,6 +928,29 @@ int csr_build(uint64_t n, uint64_t num_edges, const void *src, const void *dst, 
     }
     if (id_bytes == 4) return run_csr<int32_t, uint64_t>(P, src, dst, row_ptr, col, degree_hist32, num_duplicates, ws, s);
     return run_csr<int64_t, uint64_t>(P, src, dst, row_ptr, col, degree_hist32, num_duplicates, ws, s);
+}
+
+}  // namespace sfg
+
+namespace sfg {
+
+size_t csr_xor_workspace_bytes(uint64_t n, uint64_t num_entries) {
+    return make_plan(n, num_entries, 8, 0, false, true, 0).total;
+}
+
+int csr_xor_build(uint64_t n, uint64_t num_entries, uint64_t split, const void *src, const void *dst, int id_bytes,
+                  uint64_t *row_ptr, void *col, void *workspace, size_t workspace_bytes, hipStream_t s) {
+    if (n > (1ull << 31)) return fail(SFG_ERANGE, "xor: n above 2^31 does not fit the tagged key");
+    Plan P = make_plan(n, num_entries, id_bytes, 0, false, true, split);
+    if (workspace_bytes < P.total)
+        return fail(SFG_ENOSPACE, "xor: workspace has %zu bytes, needs %zu", workspace_bytes, P.total);
+    char *ws = static_cast<char *>(workspace);
+    if (P.key_bytes == 4) {
+        if (id_bytes == 4) return run_csr<int32_t, uint32_t>(P, src, dst, row_ptr, col, nullptr, nullptr, ws, s);
+        return run_csr<int64_t, uint32_t>(P, src, dst, row_ptr, col, nullptr, nullptr, ws, s);
+    }
+    if (id_bytes == 4) return run_csr<int32_t, uint64_t>(P, src, dst, row_ptr, col, nullptr, nullptr, ws, s);
+    return run_csr<int64_t, uint64_t>(P, src, dst, row_ptr, col, nullptr, nullptr, ws, s);
 }
 
 }  // namespace sfg

@@ -46,6 +46,11 @@ SIGNATURES = {
     "graph_stats_workspace_bytes": (_sz, [_u64, _u64, _i32]),
     "graph_stats": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _u64, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "path_stats_workspace_bytes": (_sz, [_u64]),
+    "block_matrix": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _vp, _vp]),
+    "kron_xor_random_workspace_bytes": (_sz, [_u32, _vp, _u32, _u64, _i32]),
+    "kron_perturbed_workspace_bytes": (_sz, [_u64]),
+    "kron_perturbed": (_i32, [_u32, _vp, _u32, _dbl, _dbl, _u64, _u32, _i32, _u64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "kron_xor_random": (_i32, [_u32, _vp, _u32, _u64, _u64, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "path_stats": (_i32, [_u64, _vp, _vp, _i32, _vp, _u32, _vp, _vp, _sz, _vp]),
     "ensemble_workspace_bytes": (_sz, [_vp, _u32, _u64]),
     "ensemble_generate": (_i32, [_vp, _u32, _u32, _u64, _u64, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -265,6 +270,63 @@ def path_stats(n, row_ptr, col, sources, *, ws=None, out=None, stream=None):
         ws = workspace(path_stats_workspace_bytes(n), row_ptr.device)
     _check(lib.path_stats(n, _ptr(row_ptr), _ptr(col), col.element_size(), srcs.ctypes.data_as(_vp), srcs.size,
                           _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def kron_perturbed(n0, seed_matrix, k, p_add, p_del, capacity, *, seed=0, graph_id=0, id_bytes=4, ws=None,
+                   stream=None):
+    """Kronecker expansion with the seed modified per meta-edge: returns
+    (src, dst) device tensors trimmed to the edge count."""
+    _require_cuda()
+    lib = load()
+    import numpy as np
+    W = np.ascontiguousarray(seed_matrix, np.float32).reshape(-1)
+    if W.size != n0 * n0:
+        raise ValueError("seed matrix must have n0*n0 entries")
+    dt = _idtype(id_bytes)
+    src = torch.empty(max(capacity, 1), dtype=dt, device="cuda")
+    dst = torch.empty(max(capacity, 1), dtype=dt, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    if ws is None:
+        ws = workspace(lib.kron_perturbed_workspace_bytes(capacity))
+    _check(lib.kron_perturbed(n0, W.ctypes.data_as(_vp), k, float(p_add), float(p_del), seed, graph_id, id_bytes,
+                              capacity, _ptr(src), _ptr(dst), _ptr(cnt), _ptr(ws), ws.numel(), _stream(stream)))
+    m = int(cnt.item())
+    return src[:m], dst[:m]
+
+
+def kron_xor_random(n0, seed_matrix, k, num_random, *, seed=0, graph_id=0, id_bytes=4, ws=None, stream=None):
+    """CSR (row_ptr, col[:row_ptr[n]]) of the Kronecker power of a 0/1 seed XOR
+    the random graph of num_random uniform pair draws."""
+    _require_cuda()
+    lib = load()
+    import numpy as np
+    W = np.ascontiguousarray(seed_matrix, np.float32).reshape(-1)
+    if W.size != n0 * n0:
+        raise ValueError("seed matrix must have n0*n0 entries")
+    e0 = int((W != 0).sum())
+    n = n0 ** k
+    need = int(lib.kron_xor_random_workspace_bytes(n0, W.ctypes.data_as(_vp), k, num_random, id_bytes))
+    if need == 0:  # rejected arguments: let the library say why, before allocating anything
+        _check(lib.kron_xor_random(n0, W.ctypes.data_as(_vp), k, num_random, seed, graph_id, id_bytes, None, None,
+                                   None, 0, _stream(stream)))
+    if ws is None:
+        ws = workspace(need)
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    col = torch.empty(max(e0 ** k + num_random, 1), dtype=_idtype(id_bytes), device="cuda")
+    _check(lib.kron_xor_random(n0, W.ctypes.data_as(_vp), k, num_random, seed, graph_id, id_bytes, _ptr(row_ptr),
+                               _ptr(col), _ptr(ws), ws.numel(), _stream(stream)))
+    return row_ptr, col
+
+
+def block_matrix(n, src, dst, blocks, *, out=None, stream=None):
+    """Coarse adjacency matrix [blocks, blocks] (int64 device tensor)."""
+    _require_cuda()
+    assert src.dtype == dst.dtype and src.numel() == dst.numel()
+    if out is None:
+        out = torch.empty((blocks, blocks), dtype=torch.int64, device=src.device)
+    _check(load().block_matrix(n, src.numel(), _ptr(src), _ptr(dst), src.element_size(), blocks, _ptr(out),
+                               _stream(stream)))
     return out
 
 

@@ -107,3 +107,20 @@ def small_ensemble_table(count=48, seed=23, log2_n=(10, 14), k_range=(10, 14), p
             k = int(rng.integers(k_range[0], k_range[1] + 1))
             rows.append(dict(kind="kron", graph_id=g, n0=2, initiator=W, k=k, num_edges=16 << k, seed=seed))
     return rows
+
+
+def faction_groups(num_parts, groups, overlap=False):
+    """Faction table of a block community topology: partition q belongs to
+    group g = floor(q groups / P), whose partitions form one faction; with
+    overlap, q's list also holds the next group's partitions (factions that
+    share members).  Returns (faction_off, faction_members) for pba_generate."""
+    members_of = [[q for q in range(num_parts) if q * groups // num_parts == g] for g in range(groups)]
+    off, mem = [0], []
+    for q in range(num_parts):
+        g = q * groups // num_parts
+        lst = list(members_of[g])
+        if overlap:
+            lst += members_of[(g + 1) % groups]
+        mem += lst
+        off.append(len(mem))
+    return np.array(off, np.uint32), np.array(mem, np.uint32)

@@ -1,0 +1,67 @@
+"""Community structure (Results, community figure): the coarse adjacency
+matrix on the GPU against the oracle and the Kronecker-power closed form, and
+PBA with block faction topologies, whose edges stay inside the factions."""
+import numpy as np
+import pytest
+
+from paper_1003_3684_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def test_kronecker_power_blocks(sfg, orc):
+    import torch
+    seed = wl.FIG2_SEED
+    n0, e0, k = 5, 11, 5
+    n, E = n0 ** k, e0 ** k
+    src, dst = sfg.kron_generate(n0, seed.astype(np.float32), k, E, mode=sfg.KRON_ENUMERATE)
+    power = np.ones((1, 1), np.int64)
+    for l in range(0, 4):
+        B = n0 ** l
+        got = sfg.block_matrix(n, src, dst, B).cpu().numpy()
+        np.testing.assert_array_equal(got, power * e0 ** (k - l))
+        power = np.kron(power, seed.astype(np.int64))
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("blocks", [1, 3, 64, 65, 1000])
+def test_random_edges_match_oracle(sfg, orc, blocks):
+    import torch
+    rng = np.random.default_rng(blocks)
+    n, E = 100_003, 2_000_001
+    s = rng.integers(0, n, E)
+    d = rng.integers(0, n, E)
+    s[::1000] = -1   # not vertices: not counted
+    d[7::1001] = n
+    want = orc.block_matrix(n, s[(s >= 0) & (d < n)], d[(s >= 0) & (d < n)], blocks)
+    got = sfg.block_matrix(n, torch.tensor(s, device="cuda"), torch.tensor(d, device="cuda"), blocks)
+    np.testing.assert_array_equal(got.cpu().numpy().astype(np.uint64), want)
+
+
+@pytest.mark.parametrize("overlap", [False, True])
+def test_pba_block_factions(sfg, orc, overlap):
+    n, m, P, groups = 16384, 4, 16, 4
+    foff, fmem = wl.faction_groups(P, groups, overlap=overlap)
+    src, dst = sfg.pba_generate(n, m, P, 0.0, seed=21, faction_off=foff, faction_members=fmem)
+    osrc, odst = orc.pba_generate(n, m, P, 0.0, 21, 0, foff, fmem)
+    np.testing.assert_array_equal(src.cpu().numpy(), osrc)
+    np.testing.assert_array_equal(dst.cpu().numpy(), odst)
+    M = sfg.block_matrix(n, src, dst, P).cpu().numpy()
+    np.testing.assert_array_equal(M.astype(np.uint64), orc.block_matrix(n, osrc, odst, P))
+    # With no inter-faction draws, an edge of group g lands in g (or, with
+    # overlapping factions, in g + 1): the block-diagonal community structure.
+    g = np.arange(P) * groups // P
+    allowed = (g[:, None] == g[None, :])
+    if overlap:
+        allowed |= (g[None, :] == (g[:, None] + 1) % groups)
+    assert M[~allowed].sum() == 0
+    assert M[allowed].sum() == n * m
+
+
+def test_errors(sfg):
+    import torch
+    from paper_1003_3684_amd.native import SfgenError
+    s = torch.zeros(4, dtype=torch.int32, device="cuda")
+    for bad in (0, 4097, 11):
+        with pytest.raises(SfgenError):
+            sfg.block_matrix(10, s, s, bad)
