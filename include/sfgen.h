@@ -182,7 +182,9 @@ int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p_inter, con
  *                  one.
  * workspace:       device, edges_to_csr_workspace_bytes(...) bytes.
  * Errors: EINVAL (n == 0, bad flags, NULL buffers); ERANGE (ids or sizes do
- * not fit); ENOSPACE.  Ids >= n are not detected (the caller's contract).
+ * not fit); ENOSPACE.  Ids outside [0, n) are not detected (the caller's
+ * contract): the output is then unspecified, but no kernel writes or reads
+ * outside the buffers on their account.
  * ---------------------------------------------------------------------- */
 size_t edges_to_csr_workspace_bytes(uint64_t n, uint64_t num_edges, int id_bytes, uint32_t flags);
 int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes, uint32_t flags,

@@ -186,6 +186,7 @@ struct PassArgs {
     uint32_t tag;
     int tb;                 // origin bits below the entry (first pass, XOR mode)
     uint64_t split;         // first entry of origin 1
+    uint64_t nv;            // vertices (BOUND passes write column starts below it)
 };
 
 // BOUND: the input keys are ordered by destination; mark the first position
@@ -249,7 +250,8 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
             KeyT prev = __shfl_up(k[i], 1, 64);
             if (lane == 0) prev = carry;
             carry = __shfl(k[i], 63, 64);
-            if (idx < a.N && (idx == 0 || (k[i] & mask) != (prev & mask))) {
+            // (ids at or above n are not vertices: never written, never a fault)
+            if (idx < a.N && (idx == 0 || (k[i] & mask) != (prev & mask)) && (uint64_t)(k[i] & mask) < a.nv) {
                 a.csc[(uint64_t)(k[i] & mask)] = idx;
                 a.cmark[(uint64_t)(k[i] & mask)] = 1;
             }
@@ -430,7 +432,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish_plain(FinArgs a) {
         if (valid) {
             col[idx] = (IdT)(key & mask);
             const uint64_t row = (uint64_t)(key >> a.wb);
-            if (idx == 0 || row != (uint64_t)(prev >> a.wb)) {
+            if ((idx == 0 || row != (uint64_t)(prev >> a.wb)) && row < a.n) {
                 a.rp[row] = idx;
                 if (a.rp_raw) a.rp_raw[row] = idx;
                 a.mark[row] = 1;
@@ -550,7 +552,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
         if (idx < a.N) {
             const KeyT key = s_keys[fin_slot(p + 1)] >> TB, prev = s_keys[fin_slot(p)] >> TB;
             const uint64_t row = (uint64_t)(key >> a.wb);
-            if (idx == 0 || row != (uint64_t)(prev >> a.wb)) {
+            if ((idx == 0 || row != (uint64_t)(prev >> a.wb)) && row < a.n) {
                 a.rp[row] = c;
                 if (a.rp_raw) a.rp_raw[row] = idx;
                 a.mark[row] = 1;
@@ -845,7 +847,7 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
             KeyT *out = (remaining % 2 == 0) ? keysA : keysB;
             KeyT *in = (remaining % 2 == 0) ? keysB : keysA;
             PassArgs a{P.E, P.N, src, dst, in, out, status, gbase + p * kRadix, ghist + p * kRadix, tickets + p, err,
-                       csc, cmark, P.db, 8 * p, (uint32_t)(p + 1), P.tb, P.split};
+                       csc, cmark, P.db, 8 * p, (uint32_t)(p + 1), P.tb, P.split, P.n};
             const int g = (int)P.pass_tiles;
             if (csc && p == P.dpasses) {
                 { ProfScope _ps("radix_pass", s); radix_pass<IdT, KeyT, false, false, true><<<g, kPassThreads, 0, s>>>(a); }

@@ -95,7 +95,8 @@ __global__ __launch_bounds__(kPathThreads) void ps_level_light(const uint64_t *r
         uint64_t acc = 0;
         if (seen != all)
             for (uint64_t e = e0; e < e1; ++e) {
-                acc |= front[(uint64_t)col[e]];
+                const uint64_t x = (uint64_t)col[e];
+                if (x < n) acc |= front[x];  // ids at or above n are not vertices
                 if ((acc | seen) == all) break;
             }
         const uint64_t fresh = acc & ~seen;
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kPathThreads) void ps_level_light(const uint64_t *r
 
 // Heavy vertices, one wavefront each.
 template <typename IdT>
-__global__ __launch_bounds__(kPathThreads) void ps_level_heavy(const uint64_t *rp, const IdT *col,
+__global__ __launch_bounds__(kPathThreads) void ps_level_heavy(const uint64_t *rp, const IdT *col, uint64_t n,
                                                               const uint64_t *heavy, const unsigned long long *nheavy,
                                                               uint64_t all, uint64_t *vis, const uint64_t *front,
                                                               uint64_t *next, unsigned long long *cnt) {
@@ -126,7 +127,10 @@ __global__ __launch_bounds__(kPathThreads) void ps_level_heavy(const uint64_t *r
         if (seen != all)
             for (uint64_t base = e0; base < e1; base += 64) {
                 const uint64_t e = base + lane;
-                if (e < e1) acc |= front[(uint64_t)col[e]];
+                if (e < e1) {
+                    const uint64_t x = (uint64_t)col[e];
+                    if (x < n) acc |= front[x];
+                }
                 // OR over the wave; the whole wave stops once the group is
                 // complete for v.
                 for (int off = 32; off > 0; off >>= 1) acc |= __shfl_xor(acc, off, 64);
@@ -189,7 +193,7 @@ int run_paths(uint64_t n, const uint64_t *rp, const IdT *col, const int64_t *sou
         for (uint64_t level = 1; level <= n; ++level) {
             ps_fill<unsigned long long><<<1, 64, 0, s>>>(cnt, 1, 0);
             { ProfScope _ps("path_level", s); ps_level_light<IdT><<<g, kPathThreads, 0, s>>>(rp, col, n, all, vis, fa, fb, cnt); }
-            { ProfScope _ps("path_level", s); ps_level_heavy<IdT><<<g, kPathThreads, 0, s>>>(rp, col, heavy, nheavy, all, vis, fa, fb, cnt); }
+            { ProfScope _ps("path_level", s); ps_level_heavy<IdT><<<g, kPathThreads, 0, s>>>(rp, col, n, heavy, nheavy, all, vis, fa, fb, cnt); }
             ps_accumulate<<<1, 1, 0, s>>>(cnt, level, out);
             unsigned long long found = 0;
             if (hipMemcpyAsync(&found, cnt, sizeof(found), hipMemcpyDeviceToHost, s) != hipSuccess ||

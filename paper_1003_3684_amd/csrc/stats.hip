@@ -215,6 +215,7 @@ struct WedgeArgs {
     const void *col;
     uint32_t key0, key1;
     unsigned long long *closed;  // indexed by StatGraph::out
+    uint64_t nv;                 // vertices of the shared space
 };
 
 // Sample i of graph g: Philox block (i, 0, 0, WEDGE | gid << 8).
@@ -246,7 +247,9 @@ template <typename IdT> __global__ __launch_bounds__(256) void wedge_sample(Wedg
         uint32_t y = uidx32(w.w3, d - 1);
         if (y >= x) ++y;
         const uint64_t na = (uint64_t)col[a.rp[v] + x], nb = (uint64_t)col[a.rp[v] + y];
-        if (adjacent<IdT>(a.rp, col, na, nb)) atomicAdd(&a.closed[g.out], 1ull);
+        // (ids outside the vertex space come only from invalid input; they
+        // are never looked up)
+        if (na < a.nv && adjacent<IdT>(a.rp, col, na, nb)) atomicAdd(&a.closed[g.out], 1ull);
     }
 }
 
@@ -305,7 +308,7 @@ int stats_enqueue(const StatGraph *G_dev, uint32_t count, uint64_t total_chunks,
     }
     if (samples > 0) {
         WedgeArgs wa{G_dev, count, samples, rp, pre, col, (uint32_t)seed, (uint32_t)(seed >> 32),
-                     reinterpret_cast<unsigned long long *>(closed)};
+                     reinterpret_cast<unsigned long long *>(closed), nv};
         const uint64_t items = (uint64_t)count * samples;
         const unsigned g = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((items + 255) / 256, (uint64_t)device_cu_count() * 16));
         ProfScope _ps("stats_wedge", s);

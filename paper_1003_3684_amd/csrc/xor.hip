@@ -12,8 +12,6 @@
 
 #include "common.hpp"
 
-extern "C" int kron_generate(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges, int mode,
-                             uint64_t seed, uint32_t graph_id, int id_bytes, void *src, void *dst, void *stream);
 
 namespace sfg {
 namespace {
