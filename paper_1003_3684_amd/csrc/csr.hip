@@ -511,35 +511,46 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
             nkeep += keep;
         }
     }
-    // Exclusive scan of kept counts over the threads, then over tiles.
+    // Exclusive scan of kept counts over the threads, then over tiles by a
+    // decoupled look-back in which the first wavefront reads 64 predecessors
+    // per round trip: the nearest one with an inclusive prefix ends the walk,
+    // the counts of the ones before it are added.
     uint64_t tot;
     const uint64_t ex = block_exclusive_scan_256(nkeep, s_tmp, &tot);
-    if (tid == 0) {
+    if (tid < 64) {
+        const uint32_t lane = tid;
         uint64_t *st = a.status + tile;
         uint64_t prefix = 0;
         if (tile == 0) {
-            store_agent(st, status_word(1, kFlagIncl, tot));
+            if (lane == 0) store_agent(st, status_word(1, kFlagIncl, tot));
         } else {
-            store_agent(st, status_word(1, kFlagAgg, tot));
-            uint64_t j = tile - 1;
+            if (lane == 0) store_agent(st, status_word(1, kFlagAgg, tot));
+            uint64_t j = tile;  // this round reads tiles j-1 .. j-64
             for (;;) {
-                uint64_t v = load_agent(a.status + j);
+                const bool real = j > lane;
+                const uint64_t *pj = a.status + (real ? j - 1 - lane : 0);
+                uint64_t v = real ? load_agent(pj) : status_word(1, kFlagIncl, 0);
                 uint32_t spins = 0;
                 while ((uint32_t)(v >> 58) != 1u) {
                     if (++spins > kSpinLimit || ((spins & 1023) == 0 && load_agent(a.err) != 0)) {
                         raise_device_error(a.err, DEVERR_LOOKBACK);
+                        v = status_word(1, kFlagIncl, 0);
                         break;
                     }
                     __builtin_amdgcn_s_sleep(1);
-                    v = load_agent(a.status + j);
+                    v = load_agent(pj);
                 }
-                prefix += v & ((1ull << 56) - 1);
-                if (((v >> 56) & 3) == kFlagIncl || (uint32_t)(v >> 58) != 1u || j == 0) break;
-                --j;
+                const uint64_t incl = __ballot(((v >> 56) & 3) == kFlagIncl);
+                const uint32_t first = incl ? (uint32_t)__builtin_ctzll(incl) : 64u;
+                uint64_t c = lane <= first ? (v & ((1ull << 56) - 1)) : 0;
+                for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+                prefix += c;
+                if (incl) break;
+                j -= 64;  // j > 64 here: a lane past tile 0 reads an inclusive zero
             }
-            store_agent(st, status_word(1, kFlagIncl, prefix + tot));
+            if (lane == 0) store_agent(st, status_word(1, kFlagIncl, prefix + tot));
         }
-        s_base = prefix;
+        if (lane == 0) s_base = prefix;
     }
     __syncthreads();
     const uint64_t cbase = s_base + ex;
