@@ -470,7 +470,13 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
     // Blocked reads (16 consecutive keys per thread) would hit one LDS bank
     // for the whole wave; one pad slot per 16 keys spreads them.  Slot 0 holds
     // the key before the tile, the last slot the key after it.
-    __shared__ KeyT s_keys[kFinTile + kFinTile / 16 + 2];
+    // The same LDS later holds the tile's kept columns in output order, so
+    // the column stores are coalesced; it is sized for 8-byte elements.
+    constexpr size_t kKeyBytes = (kFinTile + kFinTile / 16 + 2) * sizeof(KeyT);
+    constexpr size_t kColBytes = kFinTile * sizeof(IdT);
+    __shared__ uint64_t s_raw[((kKeyBytes > kColBytes ? kKeyBytes : kColBytes) + 7) / 8];
+    KeyT *s_keys = reinterpret_cast<KeyT *>(s_raw);
+    IdT *s_col = reinterpret_cast<IdT *>(s_raw);
     __shared__ uint64_t s_tmp[4];
     __shared__ uint64_t s_base;
     __shared__ uint32_t s_dups[kFinThreads / 64];
@@ -556,10 +562,12 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
     const uint64_t cbase = s_base + ex;
     IdT *col = static_cast<IdT *>(a.col);
     uint64_t c = cbase;
+    IdT vals[kFinItems];
 #pragma unroll
     for (int j = 0; j < kFinItems; ++j) {
         const int p = tid * kFinItems + j;
         const uint64_t idx = t0 + p;
+        vals[j] = 0;
         if (idx < a.N) {
             const KeyT key = s_keys[fin_slot(p + 1)] >> TB, prev = s_keys[fin_slot(p)] >> TB;
             const uint64_t row = (uint64_t)(key >> a.wb);
@@ -568,9 +576,18 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
                 if (a.rp_raw) a.rp_raw[row] = idx;
                 a.mark[row] = 1;
             }
-            if ((keep_bits >> j) & 1u) col[c++] = (IdT)(key & mask);
+            vals[j] = (IdT)(key & mask);
+            c += (keep_bits >> j) & 1u;
         }
     }
+    // Kept columns to LDS in output order, then coalesced stores.
+    __syncthreads();  // every read of the keys is done
+    uint32_t r = (uint32_t)ex;
+#pragma unroll
+    for (int j = 0; j < kFinItems; ++j)
+        if ((keep_bits >> j) & 1u) s_col[r++] = vals[j];
+    __syncthreads();
+    for (uint32_t i = tid; i < (uint32_t)tot; i += kFinThreads) col[s_base + i] = s_col[i];
     if (a.dups) {
         uint32_t x = ndup;
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
