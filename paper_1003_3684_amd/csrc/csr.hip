@@ -130,19 +130,29 @@ __global__ __launch_bounds__(256) void csr_prepare(PrepArgs a) {
     const IdT *src = static_cast<const IdT *>(a.src), *dst = static_cast<const IdT *>(a.dst);
     // kPrepUnroll keys per thread are loaded before any is counted, so that
     // enough loads are in flight to cover the memory latency.
+    // Every edge is read once; with SYM its reversed entry is counted too.
     const uint64_t stride = (uint64_t)gridDim.x * 256 * kPrepUnroll;
-    for (uint64_t i0 = (uint64_t)blockIdx.x * 256 * kPrepUnroll + threadIdx.x; i0 < a.N; i0 += stride) {
-        KeyT k[kPrepUnroll];
+    for (uint64_t i0 = (uint64_t)blockIdx.x * 256 * kPrepUnroll + threadIdx.x; i0 < a.E; i0 += stride) {
+        IdT su[kPrepUnroll], du[kPrepUnroll];
 #pragma unroll
         for (int u = 0; u < kPrepUnroll; ++u) {
             const uint64_t i = i0 + (uint64_t)u * 256;
-            k[u] = i < a.N ? tagged_key<IdT, KeyT, SYM>(src, dst, a.E, i, a.wb, a.tb, a.split) : (KeyT)0;
+            su[u] = i < a.E ? src[i] : (IdT)0;
+            du[u] = i < a.E ? dst[i] : (IdT)0;
         }
 #pragma unroll
         for (int u = 0; u < kPrepUnroll; ++u) {
-            if (i0 + (uint64_t)u * 256 >= a.N) break;
+            const uint64_t i = i0 + (uint64_t)u * 256;
+            if (i >= a.E) break;
+            KeyT k = pack<IdT, KeyT>(su[u], du[u], a.wb);
+            if (a.tb) k = (KeyT)((k << 1) | (KeyT)(i >= a.split ? 1u : 0u));
             for (int p = 0; p < a.passes; ++p)
-                atomicAdd(&s_h[(p * kRadix + (uint32_t)((k[u] >> (8 * p)) & 255)) * kPrepCopies + copy], 1u);
+                atomicAdd(&s_h[(p * kRadix + (uint32_t)((k >> (8 * p)) & 255)) * kPrepCopies + copy], 1u);
+            if (SYM) {
+                const KeyT kr = pack<IdT, KeyT>(du[u], su[u], a.wb);
+                for (int p = 0; p < a.passes; ++p)
+                    atomicAdd(&s_h[(p * kRadix + (uint32_t)((kr >> (8 * p)) & 255)) * kPrepCopies + copy], 1u);
+            }
         }
     }
     __syncthreads();
@@ -390,7 +400,8 @@ __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassAr
     for (uint32_t p = tid; p < nvalid; p += kPassThreads) {
         const KeyT key = s_keys[p];
         const uint32_t dd = (uint32_t)(key >> a.shift) & 255u;
-        out[s_gpos[dd] + p] = key;
+        // Streaming store: the next pass reads the keys back from HBM anyway.
+        __builtin_nontemporal_store(key, &out[s_gpos[dd] + p]);
     }
 }
 
@@ -430,7 +441,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish_plain(FinArgs a) {
         KeyT prev = __shfl_up(key, 1, 64);
         if (lane == 0 && idx > 0 && valid) prev = K[idx - 1];
         if (valid) {
-            col[idx] = (IdT)(key & mask);
+            __builtin_nontemporal_store((IdT)(key & mask), &col[idx]);  // streaming output
             const uint64_t row = (uint64_t)(key >> a.wb);
             if ((idx == 0 || row != (uint64_t)(prev >> a.wb)) && row < a.n) {
                 a.rp[row] = idx;
@@ -587,7 +598,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
     for (int j = 0; j < kFinItems; ++j)
         if ((keep_bits >> j) & 1u) s_col[r++] = vals[j];
     __syncthreads();
-    for (uint32_t i = tid; i < (uint32_t)tot; i += kFinThreads) col[s_base + i] = s_col[i];
+    for (uint32_t i = tid; i < (uint32_t)tot; i += kFinThreads) __builtin_nontemporal_store(s_col[i], &col[s_base + i]);
     if (a.dups) {
         uint32_t x = ndup;
         for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
@@ -861,7 +872,7 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
     if (P.N > 0) {
         PrepArgs pa{P.E, P.N, src, dst, ghist, P.db, P.passes, P.tb, P.split};
         // Every histogram workgroup stays resident (32 KB of LDS each).
-        const int pg = (int)std::max<uint64_t>(1, std::min<uint64_t>((P.N + 255) / 256,
+        const int pg = (int)std::max<uint64_t>(1, std::min<uint64_t>((P.E + 255) / 256,
                                                                       (uint64_t)device_cu_count() * kPrepBlocksPerCu));
         if (P.sym)
             { ProfScope _ps("csr_prepare", s); csr_prepare<IdT, KeyT, true><<<pg, 256, 0, s>>>(pa); }
