@@ -98,7 +98,7 @@ template <int NT> __device__ __forceinline__ uint32_t bucket_of(uint32_t w, cons
 // prefix's range of words (kStraddle), where the word is compared against the
 // thresholds.  The bucket count is monotone in the word, so equal buckets at
 // both ends of a range make the entry exact for every word in it.
-constexpr int kGuideBits = 12;
+constexpr int kGuideBits = 13;
 constexpr uint32_t kGuideSize = 1u << kGuideBits;
 constexpr uint32_t kStraddle = 0x100;
 
@@ -123,19 +123,23 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
         for (uint32_t blk = 0; blk * 4 < a.k; ++blk) {
             const Block4 r = philox(elo, ehi, blk, a.tagword, a.key0, a.key1);
             const uint32_t ws[4] = {r.w0, r.w1, r.w2, r.w3};
+            // The block's four table reads go out together; the rare words
+            // whose prefix holds a threshold are decoded by comparison.
+            uint32_t ge[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ge[i] = kGuide ? (uint32_t)s_guide[ws[i] >> (32 - kGuideBits)] : kStraddle;
+            if ((ge[0] | ge[1] | ge[2] | ge[3]) & kStraddle) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (ge[i] & kStraddle) {
+                        const uint32_t b = bucket_of<NT>(ws[i], a.tm1);
+                        ge[i] = ((uint32_t)(a.lut_row >> (4 * b)) & 15u) | (((uint32_t)(a.lut_col >> (4 * b)) & 15u) << 4);
+                    }
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (blk * 4 + i < a.k) {
-                    AccT rd, cd;
-                    const uint32_t ge = kGuide ? (uint32_t)s_guide[ws[i] >> (32 - kGuideBits)] : kStraddle;
-                    if (ge & kStraddle) {
-                        const uint32_t b = bucket_of<NT>(ws[i], a.tm1);
-                        rd = (AccT)((a.lut_row >> (4 * b)) & 15u);
-                        cd = (AccT)((a.lut_col >> (4 * b)) & 15u);
-                    } else {
-                        rd = (AccT)(ge & 15u);
-                        cd = (AccT)((ge >> 4) & 15u);
-                    }
+                    const AccT rd = (AccT)(ge[i] & 15u), cd = (AccT)((ge[i] >> 4) & 15u);
                     if (POW2) {
                         u = (u << a.shift) | rd;
                         v = (v << a.shift) | cd;
