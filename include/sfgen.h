@@ -332,7 +332,9 @@ int block_matrix(uint64_t n, uint64_t num_edges, const void *src, const void *ds
  * single-graph results.
  *
  * Members are processed in batches cut greedily, in descriptor order, at
- * max_batch_edges edges: a batch shares one vertex space and edge list, goes
+ * max_batch_edges edges or 2^24 vertices, whichever comes first (a single
+ * member above either limit is a batch of its own): a batch shares one vertex
+ * space and edge list, goes
  * through each generation, sort and statistics kernel once, and reuses the
  * workspace.  descs is a host array (read before the call returns; the call
  * waits for its small table uploads).  Kronecker members need n0 <= 4 and

@@ -10,7 +10,7 @@
 // statistics and random streams are exactly those of the single-graph calls
 // with the same graph id; only the launch count changes (about forty launches
 // per batch instead of forty per graph).  Batches are cut greedily, in
-// descriptor order, at max_batch_edges edges.
+// descriptor order, at max_batch_edges edges or 2^24 vertices.
 #include <math.h>
 #include <string.h>
 
@@ -118,19 +118,26 @@ int check_desc(const sfg_graph_desc &d, uint32_t i) {
     return SFG_OK;
 }
 
+// A batch also closes before its vertex space passes 2^24: the symmetrized
+// sort key of a batch is two vertex ids wide, so up to 2^24 vertices it
+// fits 48 bits and takes six 8-bit passes; one vertex more costs a seventh
+// pass over every entry, more than the per-batch launches it saves.
+constexpr uint64_t kBatchVertexCap = 1ull << 24;
+
 // Greedy batches in descriptor order.
 std::vector<std::pair<uint32_t, uint32_t>> cut_batches(const sfg_graph_desc *d, uint32_t count, uint64_t max_edges) {
     std::vector<std::pair<uint32_t, uint32_t>> out;
     uint32_t b0 = 0;
-    uint64_t acc = 0;
+    uint64_t acc = 0, vacc = 0;
     for (uint32_t i = 0; i < count; ++i) {
-        const uint64_t e = desc_edges(d[i]);
-        if (i > b0 && acc + e > max_edges) {
+        const uint64_t e = desc_edges(d[i]), nv = desc_vertices(d[i]);
+        if (i > b0 && (acc + e > max_edges || vacc + nv > kBatchVertexCap)) {
             out.push_back({b0, i});
             b0 = i;
-            acc = 0;
+            acc = vacc = 0;
         }
         acc += e;
+        vacc += nv;
     }
     if (count > b0) out.push_back({b0, count});
     return out;
