@@ -44,7 +44,15 @@ template <int NT> __device__ __forceinline__ uint32_t bucket_of(uint32_t w, cons
     return b;
 }
 
+__device__ __forceinline__ uint32_t uniform32(uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); }
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    return make_u64(uniform32((uint32_t)x), uniform32((uint32_t)(x >> 32)));
+}
+
 // Workgroup b samples edges [(b - block0) * chunk, ...) of the member owning b.
+// The member's parameters are the same for the whole workgroup, so they are
+// moved from LDS into scalar registers: the Philox key schedule and the
+// bucket thresholds then cost no vector instructions.
 template <typename IdT, int NT>
 __global__ __launch_bounds__(kKronThreads) void kron_batch(const KGraph *G, uint32_t count, IdT *__restrict__ src,
                                                            IdT *__restrict__ dst) {
@@ -61,34 +69,42 @@ __global__ __launch_bounds__(kKronThreads) void kron_batch(const KGraph *G, uint
         s_g = G[lo];
     }
     __syncthreads();
-    const KGraph &g = s_g;
+    const uint64_t edges = uniform64(s_g.edges), ebase = uniform64(s_g.ebase), vbase = uniform64(s_g.vbase);
+    const uint64_t lut_row = uniform64(s_g.lut_row), lut_col = uniform64(s_g.lut_col);
+    const uint64_t block0 = uniform64(s_g.block0);
+    uint32_t tm1[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) tm1[i] = uniform32(s_g.tm1[i]);
+    const uint32_t k = uniform32(s_g.k), n0 = uniform32(s_g.n0), shift = uniform32(s_g.shift);
+    const uint32_t pow2 = uniform32(s_g.pow2), tagword = uniform32(s_g.tagword);
+    const uint32_t key0 = uniform32(s_g.key0), key1 = uniform32(s_g.key1);
     const uint64_t chunk = (uint64_t)kKronThreads * kKronItems;
-    const uint64_t e0 = (blockIdx.x - g.block0) * chunk;
+    const uint64_t e0 = (blockIdx.x - block0) * chunk;
     for (int it = 0; it < kKronItems; ++it) {
         const uint64_t e = e0 + (uint64_t)it * kKronThreads + threadIdx.x;
-        if (e >= g.edges) break;
-        uint64_t u = 0, v = 0;
-        for (uint32_t blk = 0; blk * 4 < g.k; ++blk) {
-            const Block4 r = philox((uint32_t)e, (uint32_t)(e >> 32), blk, g.tagword, g.key0, g.key1);
+        if (e >= edges) break;
+        uint32_t u = 0, v = 0;  // below n0^k <= 2^32
+        for (uint32_t blk = 0; blk * 4 < k; ++blk) {
+            const Block4 r = philox((uint32_t)e, (uint32_t)(e >> 32), blk, tagword, key0, key1);
             const uint32_t ws[4] = {r.w0, r.w1, r.w2, r.w3};
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                if (blk * 4 + i < g.k) {
-                    const uint32_t b = bucket_of<NT>(ws[i], g.tm1);
-                    const uint64_t rd = (g.lut_row >> (4 * b)) & 15u;
-                    const uint64_t cd = (g.lut_col >> (4 * b)) & 15u;
-                    if (g.pow2) {
-                        u = (u << g.shift) | rd;
-                        v = (v << g.shift) | cd;
+                if (blk * 4 + i < k) {
+                    const uint32_t b = bucket_of<NT>(ws[i], tm1);
+                    const uint32_t rd = (uint32_t)(lut_row >> (4 * b)) & 15u;
+                    const uint32_t cd = (uint32_t)(lut_col >> (4 * b)) & 15u;
+                    if (pow2) {
+                        u = (u << shift) | rd;
+                        v = (v << shift) | cd;
                     } else {
-                        u = u * g.n0 + rd;
-                        v = v * g.n0 + cd;
+                        u = u * n0 + rd;
+                        v = v * n0 + cd;
                     }
                 }
             }
         }
-        src[g.ebase + e] = (IdT)(g.vbase + u);
-        dst[g.ebase + e] = (IdT)(g.vbase + v);
+        src[ebase + e] = (IdT)(vbase + u);
+        dst[ebase + e] = (IdT)(vbase + v);
     }
 }
 
