@@ -42,7 +42,7 @@ constexpr uint32_t kTerm = 0x80000000u;  // terminal flag of an encoded slot
 constexpr int kXcd = 8;
 constexpr int kDrawThreads = 256;
 constexpr int kResThreads = 256;
-constexpr int kResItems = 4;
+constexpr int kResItems = 16;
 constexpr int kResTile = kResThreads * kResItems;  // slots per resolve tile
 constexpr int kSubThreads = 256;
 constexpr uint32_t kMaxParts = 4096;
