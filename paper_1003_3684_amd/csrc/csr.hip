@@ -39,7 +39,7 @@ constexpr int kLookWindow = 2;  // predecessors read per lane and look-back roun
 constexpr int kLanesPerDigit = kPassThreads / kRadix;  // look-back lanes per digit
 
 constexpr int kFinThreads = 256;
-constexpr int kFinItems = 16;
+constexpr int kFinItems = 12;  // 3,072-entry finish tiles: six workgroups per CU with 8-byte keys
 constexpr int kFinTile = kFinThreads * kFinItems;
 
 constexpr int kScanChunk = 4096;  // vertices per chunk of the row fill scan
@@ -478,8 +478,8 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish_plain(FinArgs a) {
 template <typename IdT, typename KeyT, bool XOR>
 __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
     constexpr int TB = XOR ? 1 : 0;  // origin bits below the entry
-    // Blocked reads (16 consecutive keys per thread) would hit one LDS bank
-    // for the whole wave; one pad slot per 16 keys spreads them.  Slot 0 holds
+    // Blocked reads (kFinItems consecutive keys per thread) would hit few LDS
+    // banks across the wave; one pad slot per 16 keys spreads them.  Slot 0 holds
     // the key before the tile, the last slot the key after it.
     // The same LDS later holds the tile's kept columns in output order, so
     // the column stores are coalesced; it is sized for 8-byte elements.
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(kFinThreads) void csr_finish(FinArgs a) {
     }
     __syncthreads();
     const KeyT mask = ((KeyT)1 << a.wb) - 1;
-    // Blocked view: thread t owns positions t*16 .. t*16+15 of the tile.
+    // Blocked view: thread t owns positions t*kFinItems .. (t+1)*kFinItems-1.
     uint32_t keep_bits = 0, nkeep = 0, ndup = 0;
 #pragma unroll
     for (int j = 0; j < kFinItems; ++j) {
