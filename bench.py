@@ -310,12 +310,19 @@ def _bench_mlp(sfg, torch, batch=4096, steps=50):
             "note": "launch-bound: a 256-wide network is far below the matrix-core roofline"}
 
 
-def _bench_ensemble(sfg, wl, torch, samples=10_000, stat_seed=5, max_batch_edges=1 << 30):
+def _bench_ensemble(sfg, wl, torch, samples=10_000, stat_seed=5,
+                    candidates=(1 << 26, 1 << 27, 1 << 28, 1 << 30)):
     """Graphs/s of the batched ensemble entry point against the same 4,096
     graphs made one by one (generator call, then the statistics call), with
-    the statistics compared member by member."""
+    the statistics compared member by member.  The batch budget is chosen
+    first by the autotuner over `candidates` (each runs the whole table once;
+    the tuner checks that all give the same statistics)."""
     import numpy as np
+    from paper_1003_3684_amd import tune
     rows = wl.ensemble_table()
+    tuned = tune.tune_ensemble(rows, candidates=candidates, num_samples=samples, stat_seed=stat_seed, save=False)
+    max_batch_edges = tuned["best"]
+    torch.cuda.empty_cache()
     descs = sfg.graph_descs(rows)
     count = len(rows)
     edges = sum(r["n"] * r["m"] if r["kind"] == "pba" else r["num_edges"] for r in rows)
@@ -377,6 +384,7 @@ def _bench_ensemble(sfg, wl, torch, samples=10_000, stat_seed=5, max_batch_edges
     torch.cuda.empty_cache()
     return {"workload": f"ensemble_{count}_graphs_seed17", "graphs": count, "edges": edges,
             "wedge_samples": samples, "max_batch_edges": max_batch_edges,
+            "tuner_seconds": {str(c): round(t, 4) for c, t in tuned["seconds"].items()},
             "batched_s": batched_s, "batched_graphs_per_s": count / batched_s,
             "batched_edges_per_s": edges / batched_s,
             "plain_s": plain_s, "plain_wall_s": plain_wall, "plain_graphs_per_s": count / plain_s,

@@ -4,10 +4,12 @@ The library (libsfgen.so, HIP kernels behind the C ABI in include/sfgen.h)
 implements the parallel Barabasi-Albert and Kronecker generators of Yoo &
 Henderson, "Parallel Generation of Massive Scale-Free Graphs", and the CSR
 build with degree histogram that follows them.  ``native`` holds the ctypes
-binding; ``workloads`` the seeded synthetic workload definitions.
+binding; ``workloads`` the seeded synthetic workload definitions;
+``surrogate`` the MLP surrogate and its inversion; ``tune`` the autotuner of
+the ensemble's batch schedule.
 """
 
-__all__ = ["native", "workloads"]
+__all__ = ["native", "workloads", "surrogate", "tune"]
 
 
 def __getattr__(name):
