@@ -94,62 +94,74 @@ template <int NT> __device__ __forceinline__ uint32_t bucket_of(uint32_t w, cons
 }
 
 // Guide table over the top kGuideBits bits of a word: for every prefix the
-// (row, column) digits of the cell, unless a threshold falls inside the
-// prefix's range of words (kStraddle), where the word is compared against the
-// thresholds.  The bucket count is monotone in the word, so equal buckets at
-// both ends of a range make the entry exact for every word in it.
+// row digit and the column digit of the cell (two byte tables, so that each
+// digit is shifted into its id by a single instruction), unless a threshold
+// falls inside the prefix's range of words (kStraddle in the row byte), where
+// the word is compared against the thresholds.  The bucket count is monotone
+// in the word, so equal buckets at both ends of a range make the entry exact
+// for every word in it.
 constexpr int kGuideBits = 13;
 constexpr uint32_t kGuideSize = 1u << kGuideBits;
-constexpr uint32_t kStraddle = 0x100;
+constexpr uint32_t kStraddle = 0x80;
 
 template <typename IdT, typename AccT, bool POW2, int NT>
 __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__restrict__ src, IdT *__restrict__ dst) {
     // With few thresholds the comparisons are cheaper than the table.
     constexpr bool kGuide = NT > 3;
-    __shared__ uint16_t s_guide[kGuide ? kGuideSize : 1];
+    __shared__ uint8_t s_guide[kGuide ? 2 * kGuideSize : 1];  // row digits | kStraddle, then column digits
     if (kGuide) {
         for (uint32_t i = threadIdx.x; i < kGuideSize; i += kBlock) {
             const uint32_t lo = i << (32 - kGuideBits), hi = lo | ((1u << (32 - kGuideBits)) - 1u);
             const uint32_t blo = bucket_of<NT>(lo, a.tm1), bhi = bucket_of<NT>(hi, a.tm1);
             const uint32_t rd = (uint32_t)(a.lut_row >> (4 * blo)) & 15u, cd = (uint32_t)(a.lut_col >> (4 * blo)) & 15u;
-            s_guide[i] = (uint16_t)(rd | (cd << 4) | (blo == bhi ? 0u : kStraddle));
+            s_guide[i] = (uint8_t)(rd | (blo == bhi ? 0u : kStraddle));
+            s_guide[kGuideSize + i] = (uint8_t)cd;
         }
         __syncthreads();
     }
+    // Levels 4 blk .. 4 blk + nlev - 1 of edge (elo, ehi) from Philox block blk.
+    auto levels = [&](uint32_t elo, uint32_t ehi, uint32_t blk, uint32_t nlev, AccT &u, AccT &v) {
+        const Block4 r = philox(elo, ehi, blk, a.tagword, a.key0, a.key1);
+        const uint32_t ws[4] = {r.w0, r.w1, r.w2, r.w3};
+        // The block's table reads go out together; the rare words whose
+        // prefix holds a threshold are decoded by comparison.
+        uint32_t rd[4], cd[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const uint32_t g = ws[i] >> (32 - kGuideBits);
+            rd[i] = kGuide ? (uint32_t)s_guide[g] : kStraddle;
+            cd[i] = kGuide ? (uint32_t)s_guide[kGuideSize + g] : 0u;
+        }
+        if ((rd[0] | rd[1] | rd[2] | rd[3]) & kStraddle) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (rd[i] & kStraddle) {
+                    const uint32_t b = bucket_of<NT>(ws[i], a.tm1);
+                    rd[i] = (uint32_t)(a.lut_row >> (4 * b)) & 15u;
+                    cd[i] = (uint32_t)(a.lut_col >> (4 * b)) & 15u;
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            if ((uint32_t)i < nlev) {
+                if (POW2) {
+                    u = (u << a.shift) | (AccT)rd[i];
+                    v = (v << a.shift) | (AccT)cd[i];
+                } else {
+                    u = u * a.n0 + (AccT)rd[i];
+                    v = v * a.n0 + (AccT)cd[i];
+                }
+            }
+        }
+    };
+    // Whole blocks of four levels first (no per-level test), then the rest.
+    const uint32_t full = a.k / 4, rest = a.k % 4;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < a.num_edges; e += stride) {
         AccT u = 0, v = 0;
         const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
-        for (uint32_t blk = 0; blk * 4 < a.k; ++blk) {
-            const Block4 r = philox(elo, ehi, blk, a.tagword, a.key0, a.key1);
-            const uint32_t ws[4] = {r.w0, r.w1, r.w2, r.w3};
-            // The block's four table reads go out together; the rare words
-            // whose prefix holds a threshold are decoded by comparison.
-            uint32_t ge[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ge[i] = kGuide ? (uint32_t)s_guide[ws[i] >> (32 - kGuideBits)] : kStraddle;
-            if ((ge[0] | ge[1] | ge[2] | ge[3]) & kStraddle) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (ge[i] & kStraddle) {
-                        const uint32_t b = bucket_of<NT>(ws[i], a.tm1);
-                        ge[i] = ((uint32_t)(a.lut_row >> (4 * b)) & 15u) | (((uint32_t)(a.lut_col >> (4 * b)) & 15u) << 4);
-                    }
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (blk * 4 + i < a.k) {
-                    const AccT rd = (AccT)(ge[i] & 15u), cd = (AccT)((ge[i] >> 4) & 15u);
-                    if (POW2) {
-                        u = (u << a.shift) | rd;
-                        v = (v << a.shift) | cd;
-                    } else {
-                        u = u * a.n0 + rd;
-                        v = v * a.n0 + cd;
-                    }
-                }
-            }
-        }
+        for (uint32_t blk = 0; blk < full; ++blk) levels(elo, ehi, blk, 4, u, v);
+        if (rest) levels(elo, ehi, full, rest, u, v);
         src[e] = (IdT)u;
         dst[e] = (IdT)v;
     }
