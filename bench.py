@@ -11,8 +11,11 @@ itself; every buffer is resident in HBM before the timed region starts.
 One JSON line is printed.  Besides the headline edges/s it carries the
 roofline of the dominant kernel (the radix-sort pass), the CPU oracle timed
 on a bounded sample of the same workload, the PBA workload (2^27 vertices,
-m = 5, 1,024 partitions) and the batched-versus-plain ensemble rate (4,096
-PBA and Kronecker graphs with their statistics).
+m = 5, 1,024 partitions), PBA generation at the paper's largest size (2^30
+vertices, m = 5), the batched-versus-plain ensemble rate (4,096 PBA and
+Kronecker graphs with their statistics, batch budget from the autotuner),
+the enumerated Kronecker power of the Fig. 2 seed and one surrogate training
+step.
 """
 import argparse
 import hashlib
@@ -191,11 +194,41 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_extras:
-        result["extras"] = {"pba": _bench_pba(sfg, wl, torch), "ensemble": _bench_ensemble(sfg, wl, torch),
+        result["extras"] = {"pba": _bench_pba(sfg, wl, torch), "pba_paper_scale": _bench_pba_paper(sfg, wl, torch),
+                            "ensemble": _bench_ensemble(sfg, wl, torch),
                             "kron_enumerate": _bench_enumerate(sfg, wl, torch), "mlp": _bench_mlp(sfg, torch)}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_sample)
     print(json.dumps(result), flush=True)
+
+
+def _bench_pba_paper(sfg, wl, torch, reps=2):
+    """PBA generation at the paper's largest size: 2^30 vertices, m = 5
+    (5.4e9 edges, int32), 1,024 partitions, p = 0.1; edge list only, as the
+    paper times it.  For context, the paper generates 1 billion vertices and
+    5 billion edges in under 13 s on a 1,024-processor cluster."""
+    c = wl.PBA_PAPER
+    E = c["n"] * c["m"]
+    src = torch.empty(E, dtype=torch.int32, device="cuda")
+    dst = torch.empty(E, dtype=torch.int32, device="cuda")
+    ws = sfg.workspace(sfg.pba_workspace_bytes(c["n"], c["m"], c["num_parts"]))
+
+    def gen():
+        sfg.pba_generate(c["n"], c["m"], c["num_parts"], c["p_inter"], seed=c["seed"], src=src, dst=dst, ws=ws)
+
+    gen()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        gen()
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst, ws
+    torch.cuda.empty_cache()
+    return {"workload": c["name"], "edges": E, "gen_ms": ms, "gen_edges_per_s": E / (ms / 1e3),
+            "paper_context": "under 13 s for 1e9 vertices and 5e9 edges on 1,024 processors of a cluster"}
 
 
 def _bench_pba(sfg, wl, torch, reps=3):
