@@ -114,6 +114,23 @@ int kron_generate(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_
                   uint64_t seed, uint32_t graph_id, int id_bytes, void *src, void *dst, void *stream);
 
 /* ------------------------------------------------------------------------
+ * kron_generate_range -- edges [e_begin, e_begin + count) of the graph that
+ * kron_generate(n0, initiator, k, num_edges, mode, seed, graph_id, ...)
+ * writes, into src[0 .. count) and dst[0 .. count).  Every edge is a
+ * function of its index alone (the PK meta-edges are independent, section
+ * "Parallel Kronecker (PK) method"; in sample mode the index is the Philox
+ * counter), so a graph can be generated in chunks, resumed after an
+ * interruption from its last finished chunk, or split across devices, and
+ * the pieces equal the corresponding slices of the one-call output.
+ * kron_generate is this call with e_begin = 0 and count = num_edges.
+ * Errors: those of kron_generate, and EINVAL when e_begin + count exceeds
+ * num_edges.
+ * ---------------------------------------------------------------------- */
+int kron_generate_range(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges, uint64_t e_begin,
+                        uint64_t count, int mode, uint64_t seed, uint32_t graph_id, int id_bytes, void *src,
+                        void *dst, void *stream);
+
+/* ------------------------------------------------------------------------
  * pba_generate -- parallel Barabasi-Albert edges (section "Parallel
  * Barabasi-Albert (PBA) method", Fig. 1).
  *

@@ -6,10 +6,11 @@ Henderson, "Parallel Generation of Massive Scale-Free Graphs", and the CSR
 build with degree histogram that follows them.  ``native`` holds the ctypes
 binding; ``workloads`` the seeded synthetic workload definitions;
 ``surrogate`` the MLP surrogate and its inversion; ``tune`` the autotuner of
-the ensemble's batch schedule.
+the ensemble's batch schedule; ``chunked`` range-chunked Kronecker generation
+with resume.
 """
 
-__all__ = ["native", "workloads", "surrogate", "tune"]
+__all__ = ["native", "workloads", "surrogate", "tune", "chunked"]
 
 
 def __getattr__(name):

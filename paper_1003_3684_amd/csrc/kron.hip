@@ -79,7 +79,8 @@ namespace {
 // digits below 16): thresholds live in scalar registers, the bucket-to-digit
 // map in two 64-bit nibble tables.
 struct FastArgs {
-    uint64_t num_edges;
+    uint64_t num_edges;  // edges written: e_begin .. e_begin + num_edges - 1
+    uint64_t e_begin;
     uint32_t key0, key1, tagword, k;
     uint32_t n0, shift;
     uint32_t tm1[15];
@@ -157,19 +158,20 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
     // Whole blocks of four levels first (no per-level test), then the rest.
     const uint32_t full = a.k / 4, rest = a.k % 4;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < a.num_edges; e += stride) {
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < a.num_edges; i += stride) {
         AccT u = 0, v = 0;
+        const uint64_t e = a.e_begin + i;  // the edge's index in the whole graph
         const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
         for (uint32_t blk = 0; blk < full; ++blk) levels(elo, ehi, blk, 4, u, v);
         if (rest) levels(elo, ehi, full, rest, u, v);
-        src[e] = (IdT)u;
-        dst[e] = (IdT)v;
+        src[i] = (IdT)u;
+        dst[i] = (IdT)v;
     }
 }
 
 // General path: up to 255 distinct thresholds, searched in LDS.
 struct GeneralArgs {
-    uint64_t num_edges;
+    uint64_t num_edges, e_begin;
     uint32_t key0, key1, tagword, k;
     uint32_t n0, nt;
 };
@@ -186,8 +188,9 @@ __global__ __launch_bounds__(kBlock) void kron_sample_general(GeneralArgs a, Sam
     }
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < a.num_edges; e += stride) {
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < a.num_edges; i += stride) {
         AccT u = 0, v = 0;
+        const uint64_t e = a.e_begin + i;  // the edge's index in the whole graph
         const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
         for (uint32_t blk = 0; blk * 4 < a.k; ++blk) {
             const Block4 r = philox(elo, ehi, blk, a.tagword, a.key0, a.key1);
@@ -206,15 +209,15 @@ __global__ __launch_bounds__(kBlock) void kron_sample_general(GeneralArgs a, Sam
                 }
             }
         }
-        src[e] = (IdT)u;
-        dst[e] = (IdT)v;
+        src[i] = (IdT)u;
+        dst[i] = (IdT)v;
     }
 }
 
 // Enumerate mode.  mask holds the 0/1 seed matrix (n0 <= 64) as bits; every
 // block rebuilds the row-major list of nonzero cells in LDS.
 struct EnumArgs {
-    uint64_t num_edges;
+    uint64_t num_edges, e_begin;
     uint32_t n0, e0, k;
     uint32_t mask[128];
 };
@@ -246,8 +249,8 @@ __global__ __launch_bounds__(kBlock) void kron_enumerate_kernel(EnumArgs a, IdT 
     }
     __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < a.num_edges; e += stride) {
-        IdxT rest = (IdxT)e;
+    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < a.num_edges; i += stride) {
+        IdxT rest = (IdxT)(a.e_begin + i);
         uint64_t u = 0, v = 0, pw = 1;
         for (uint32_t l = 0; l < a.k; ++l) {  // least significant digit first
             const IdxT q = rest / a.e0;
@@ -257,8 +260,8 @@ __global__ __launch_bounds__(kBlock) void kron_enumerate_kernel(EnumArgs a, IdT 
             v += (uint64_t)s_c[d] * pw;
             pw *= a.n0;
         }
-        src[e] = (IdT)u;
-        dst[e] = (IdT)v;
+        src[i] = (IdT)u;
+        dst[i] = (IdT)v;
     }
 }
 
@@ -305,13 +308,24 @@ using namespace sfg;
 
 extern "C" int kron_generate(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges, int mode,
                              uint64_t seed, uint32_t graph_id, int id_bytes, void *src, void *dst, void *stream) {
+    return kron_generate_range(n0, initiator, k, num_edges, 0, num_edges, mode, seed, graph_id, id_bytes, src, dst,
+                               stream);
+}
+
+extern "C" int kron_generate_range(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges,
+                                   uint64_t e_begin, uint64_t count, int mode, uint64_t seed, uint32_t graph_id,
+                                   int id_bytes, void *src, void *dst, void *stream) {
     if (n0 < 2) return fail(SFG_EINVAL, "kron_generate: n0 must be >= 2 (got %u)", n0);
     if (k == 0) return fail(SFG_EINVAL, "kron_generate: k must be >= 1");
     if (!initiator) return fail(SFG_EINVAL, "kron_generate: initiator is NULL");
     if (mode != SFG_KRON_SAMPLE && mode != SFG_KRON_ENUMERATE) return fail(SFG_EINVAL, "kron_generate: bad mode %d", mode);
     if (id_bytes != 4 && id_bytes != 8) return fail(SFG_EINVAL, "kron_generate: id_bytes must be 4 or 8");
     if (graph_id >= (1u << 24)) return fail(SFG_EINVAL, "kron_generate: graph_id must be < 2^24");
-    if (num_edges > 0 && (!src || !dst)) return fail(SFG_EINVAL, "kron_generate: NULL output buffer");
+    if (e_begin > num_edges || count > num_edges - e_begin)
+        return fail(SFG_EINVAL, "kron_generate: edges [%llu, %llu + %llu) exceed the graph's %llu",
+                    (unsigned long long)e_begin, (unsigned long long)e_begin, (unsigned long long)count,
+                    (unsigned long long)num_edges);
+    if (count > 0 && (!src || !dst)) return fail(SFG_EINVAL, "kron_generate: NULL output buffer");
     const uint64_t nv = upow(n0, k);
     const uint64_t max_id = id_bytes == 4 ? 0x7FFFFFFFull : 0x7FFFFFFFFFFFFFFFull;
     if (nv == 0 || nv - 1 > max_id)
@@ -340,11 +354,13 @@ extern "C" int kron_generate(uint32_t n0, const float *initiator, uint32_t k, ui
         if (ne == 0 || ne != num_edges)
             return fail(SFG_EINVAL, "kron_generate: enumerate mode writes e0^k = %u^%u edges, num_edges is %llu", e0, k,
                         (unsigned long long)num_edges);
-        a.num_edges = num_edges;
+        if (count == 0) return SFG_OK;
+        a.num_edges = count;
+        a.e_begin = e_begin;
         a.n0 = n0;
         a.e0 = e0;
         a.k = k;
-        const int g = grid_for(num_edges);
+        const int g = grid_for(count);
         const bool idx32 = ne <= (1ull << 32);
         if (id_bytes == 4 && idx32)
             { ProfScope _ps("kron_enumerate", s); kron_enumerate_kernel<int32_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst); }
@@ -362,13 +378,14 @@ extern "C" int kron_generate(uint32_t n0, const float *initiator, uint32_t k, ui
     memset(&tab, 0, sizeof(tab));
     int rc = build_sample_table(n0, initiator, tab);
     if (rc != SFG_OK) return rc;
-    if (num_edges == 0) return SFG_OK;
+    if (count == 0) return SFG_OK;
     const uint32_t key0 = (uint32_t)seed, key1 = (uint32_t)(seed >> 32);
     const uint32_t tagword = TAG_KRON | (graph_id << 8);
     if (tab.nt <= 15) {
         FastArgs a;
         memset(&a, 0, sizeof(a));
-        a.num_edges = num_edges;
+        a.num_edges = count;
+        a.e_begin = e_begin;
         a.key0 = key0;
         a.key1 = key1;
         a.tagword = tagword;
@@ -389,14 +406,15 @@ extern "C" int kron_generate(uint32_t n0, const float *initiator, uint32_t k, ui
         return check_launch("kron_generate(sample)");
     }
     GeneralArgs a;
-    a.num_edges = num_edges;
+    a.num_edges = count;
+    a.e_begin = e_begin;
     a.key0 = key0;
     a.key1 = key1;
     a.tagword = tagword;
     a.k = k;
     a.n0 = n0;
     a.nt = tab.nt;
-    const int g = grid_for(num_edges);
+    const int g = grid_for(count);
     if (id_bytes == 4)
         { ProfScope _ps("kron_sample", s); kron_sample_general<int32_t, uint32_t><<<g, kBlock, 0, s>>>(a, tab, (int32_t *)src, (int32_t *)dst); }
     else if (acc32)

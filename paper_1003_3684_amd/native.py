@@ -39,6 +39,7 @@ SIGNATURES = {
     "sfg_profile_reset": (_i32, []),
     "sfg_profile_query": (_i32, [C.c_char_p, C.POINTER(_u64), C.POINTER(C.c_double)]),
     "kron_generate": (_i32, [_u32, _vp, _u32, _u64, _i32, _u64, _u32, _i32, _vp, _vp, _vp]),
+    "kron_generate_range": (_i32, [_u32, _vp, _u32, _u64, _u64, _u64, _i32, _u64, _u32, _i32, _vp, _vp, _vp]),
     "pba_workspace_bytes": (_sz, [_u64, _u32, _u32, _u64]),
     "pba_generate": (_i32, [_u64, _u32, _u32, _dbl, _vp, _vp, _u64, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "edges_to_csr_workspace_bytes": (_sz, [_u64, _u64, _i32, _u32]),
@@ -164,6 +165,25 @@ def kron_generate(n0, initiator, k, num_edges, *, mode=KRON_SAMPLE, seed=0, grap
         dst = torch.empty(num_edges, dtype=dt, device="cuda")
     _check(lib.kron_generate(n0, C.c_void_p(W.data_ptr()), k, num_edges, mode, seed, graph_id, id_bytes,
                              _ptr(src), _ptr(dst), _stream(stream)))
+    return src, dst
+
+
+def kron_generate_range(n0, initiator, k, num_edges, e_begin, count, *, mode=KRON_SAMPLE, seed=0, graph_id=0,
+                        id_bytes=4, src=None, dst=None, stream=None):
+    """Edges [e_begin, e_begin + count) of the graph kron_generate(n0, initiator,
+    k, num_edges, ...) writes, into device tensors of count ids."""
+    _require_cuda()
+    lib = load()
+    W = torch.as_tensor(initiator, dtype=torch.float32).contiguous().reshape(-1)
+    if W.numel() != n0 * n0:
+        raise ValueError("initiator must have n0*n0 entries")
+    dt = _idtype(id_bytes)
+    if src is None:
+        src = torch.empty(count, dtype=dt, device="cuda")
+    if dst is None:
+        dst = torch.empty(count, dtype=dt, device="cuda")
+    _check(lib.kron_generate_range(n0, C.c_void_p(W.data_ptr()), k, num_edges, e_begin, count, mode, seed, graph_id,
+                                   id_bytes, _ptr(src), _ptr(dst), _stream(stream)))
     return src, dst
 
 
