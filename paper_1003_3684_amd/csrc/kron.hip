@@ -219,13 +219,21 @@ __global__ __launch_bounds__(kBlock) void kron_sample_general(GeneralArgs a, Sam
 struct EnumArgs {
     uint64_t num_edges, e_begin;
     uint32_t n0, e0, k;
+    // Digits are taken in base `base` = e0, or e0^2 (two levels per step,
+    // through a pair table) when e0 <= 64: `steps` steps, then one single
+    // level if `odd`.  magic = floor((2^32 - 1) / base); place = n0 or n0^2.
+    uint32_t pair, base, steps, odd, magic, place;
     uint32_t mask[128];
 };
 
-template <typename IdT, typename IdxT>
+// Edge indices below 2^32 (IdxT = uint32_t) take their digits with a
+// multiply-high by `magic`: the estimate is the quotient or one less, and one
+// correction step makes it exact.  AccT holds ids (uint32_t when n0^k <= 2^32).
+template <typename IdT, typename IdxT, typename AccT>
 __global__ __launch_bounds__(kBlock) void kron_enumerate_kernel(EnumArgs a, IdT *__restrict__ src,
                                                                 IdT *__restrict__ dst) {
-    __shared__ uint16_t s_r[4096], s_c[4096];
+    __shared__ uint16_t s_r[4096], s_c[4096];    // seed edge -> (row, column)
+    __shared__ uint16_t s_r2[4096], s_c2[4096];  // pair digit hi e0 + lo -> (r_hi n0 + r_lo, ...)
     __shared__ uint32_t s_wordbase[129];
     if (threadIdx.x == 0) {
         uint32_t acc = 0;
@@ -248,17 +256,43 @@ __global__ __launch_bounds__(kBlock) void kron_enumerate_kernel(EnumArgs a, IdT 
         }
     }
     __syncthreads();
+    const bool pair = a.pair != 0;
+    if (pair) {
+        for (uint32_t D = threadIdx.x; D < a.base; D += kBlock) {
+            const uint32_t hi = D / a.e0, lo = D % a.e0;
+            s_r2[D] = (uint16_t)(s_r[hi] * a.n0 + s_r[lo]);
+            s_c2[D] = (uint16_t)(s_c[hi] * a.n0 + s_c[lo]);
+        }
+        __syncthreads();
+    }
+    const uint16_t *tr = pair ? s_r2 : s_r, *tc = pair ? s_c2 : s_c;
     const uint64_t stride = (uint64_t)gridDim.x * kBlock;
     for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < a.num_edges; i += stride) {
         IdxT rest = (IdxT)(a.e_begin + i);
-        uint64_t u = 0, v = 0, pw = 1;
-        for (uint32_t l = 0; l < a.k; ++l) {  // least significant digit first
-            const IdxT q = rest / a.e0;
-            const uint32_t d = (uint32_t)(rest - q * a.e0);
+        AccT u = 0, v = 0, pw = 1;
+        for (uint32_t l = 0; l < a.steps; ++l) {  // least significant digits first
+            IdxT q;
+            uint32_t d;
+            if (sizeof(IdxT) == 4) {
+                q = (IdxT)__umulhi((uint32_t)rest, a.magic);
+                d = (uint32_t)rest - (uint32_t)q * a.base;
+                if (d >= a.base) {
+                    ++q;
+                    d -= a.base;
+                }
+            } else {
+                q = rest / a.base;
+                d = (uint32_t)(rest - q * a.base);
+            }
             rest = q;
-            u += (uint64_t)s_r[d] * pw;
-            v += (uint64_t)s_c[d] * pw;
-            pw *= a.n0;
+            u += (AccT)tr[d] * pw;
+            v += (AccT)tc[d] * pw;
+            pw *= a.place;
+        }
+        if (a.odd) {  // the most significant level; rest < e0 here
+            const uint32_t d = (uint32_t)rest < 4095u ? (uint32_t)rest : 4095u;
+            u += (AccT)s_r[d] * pw;
+            v += (AccT)s_c[d] * pw;
         }
         src[i] = (IdT)u;
         dst[i] = (IdT)v;
@@ -360,16 +394,28 @@ extern "C" int kron_generate_range(uint32_t n0, const float *initiator, uint32_t
         a.n0 = n0;
         a.e0 = e0;
         a.k = k;
+        const bool pair = e0 <= 64;
+        a.pair = pair ? 1u : 0u;
+        a.base = pair ? e0 * e0 : e0;
+        a.steps = pair ? k / 2 : k;
+        a.odd = pair ? (k & 1) : 0;
+        a.magic = 0xFFFFFFFFu / a.base;
+        a.place = pair ? n0 * n0 : n0;
         const int g = grid_for(count);
         const bool idx32 = ne <= (1ull << 32);
-        if (id_bytes == 4 && idx32)
-            { ProfScope _ps("kron_enumerate", s); kron_enumerate_kernel<int32_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst); }
+        ProfScope _ps("kron_enumerate", s);
+        if (id_bytes == 4 && idx32)  // int32 ids: n0^k <= 2^31
+            kron_enumerate_kernel<int32_t, uint32_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst);
         else if (id_bytes == 4)
-            { ProfScope _ps("kron_enumerate", s); kron_enumerate_kernel<int32_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst); }
+            kron_enumerate_kernel<int32_t, uint64_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst);
+        else if (idx32 && acc32)
+            kron_enumerate_kernel<int64_t, uint32_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
         else if (idx32)
-            { ProfScope _ps("kron_enumerate", s); kron_enumerate_kernel<int64_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst); }
+            kron_enumerate_kernel<int64_t, uint32_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
+        else if (acc32)
+            kron_enumerate_kernel<int64_t, uint64_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
         else
-            { ProfScope _ps("kron_enumerate", s); kron_enumerate_kernel<int64_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst); }
+            kron_enumerate_kernel<int64_t, uint64_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
         return check_launch("kron_generate(enumerate)");
     }
 

@@ -89,6 +89,25 @@ def test_kron_enumerate_random(sfg, orc):
         np.testing.assert_array_equal(dst.cpu().numpy().astype(np.int64), od)
 
 
+def test_kron_enumerate_digit_pairs(sfg, orc):
+    """Two levels per digit step (e0 <= 64) and one (e0 > 64): a single seed
+    edge (e0 = 1) at odd k, the largest paired seed (e0 = 64, base 4,096) at
+    odd k, and the smallest unpaired one (e0 = 65)."""
+    full8 = np.ones((8, 8), np.uint8)
+    nine = np.zeros((9, 9), np.uint8)
+    nine.ravel()[:65] = 1
+    one = np.zeros((2, 2), np.uint8)
+    one[1, 0] = 1
+    for adj, k, ib in [(one, 5, 4), (one, 6, 8), (full8, 3, 4), (full8, 2, 8), (nine, 2, 4), (nine, 3, 8)]:
+        n0 = adj.shape[0]
+        E = int(adj.sum()) ** k
+        c = dict(n0=n0, initiator=adj.astype(np.float32), k=k, num_edges=E, id_bytes=ib)
+        src, dst = _gpu(sfg, c, mode=sfg.KRON_ENUMERATE)
+        os_, od = orc.kron_enumerate(adj, k)
+        np.testing.assert_array_equal(src.cpu().numpy().astype(np.int64), os_)
+        np.testing.assert_array_equal(dst.cpu().numpy().astype(np.int64), od)
+
+
 def _sampled_check(sfg, orc, c, n_random=2000, chunk=1 << 16):
     import torch
     src, dst = _gpu(sfg, c)
