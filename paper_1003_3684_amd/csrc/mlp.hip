@@ -163,13 +163,38 @@ __global__ void act_grad(const float *dH, const float *Z, float *dZ, bf16 *dZb, 
     }
 }
 
-// Column sums in a fixed order: db[c] = sum_r dZ[r][c] (one thread per column).
-__global__ void col_sums(const float *dZ, int rows, int cols, float *db) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= cols) return;
+// Column sums db[c] = sum_r dZ[r][c] in a fixed order, in two passes so that
+// no thread walks the whole batch: pass 1 sums row chunk blockIdx.y of 64
+// columns (four row lanes per column, interleaved rows, combined in lane
+// order) into part[chunk][c]; pass 2 sums the chunks the same way.
+constexpr int kColChunks = 64;
+
+__device__ __forceinline__ void col_sum_lanes(const float *v, int rows, int cols, int r0, int r1, float *out) {
+    __shared__ float s[4][64];
+    const int cl = threadIdx.x % 64, q = threadIdx.x / 64;
+    const int c = blockIdx.x * 64 + cl;
     float acc = 0.f;
-    for (int r = 0; r < rows; ++r) acc += dZ[(size_t)r * cols + c];
-    db[c] = acc;
+    if (c < cols)
+        for (int r = r0 + q; r < r1; r += 4) acc += v[(size_t)r * cols + c];
+    s[q][cl] = acc;
+    __syncthreads();
+    if (q == 0 && c < cols) *out = ((s[0][cl] + s[1][cl]) + s[2][cl]) + s[3][cl];
+}
+
+__global__ __launch_bounds__(256) void col_sums_chunks(const float *dZ, int rows, int cols, int chunk_rows,
+                                                       float *part) {
+    const int r0 = blockIdx.y * chunk_rows, r1 = min(rows, r0 + chunk_rows);
+    const int c = blockIdx.x * 64 + threadIdx.x % 64;
+    float tmp;
+    col_sum_lanes(dZ, r1, cols, r0, r1, &tmp);
+    if (threadIdx.x < 64 && c < cols) part[(size_t)blockIdx.y * cols + c] = tmp;
+}
+
+__global__ __launch_bounds__(256) void col_sums_total(const float *part, int chunks, int cols, float *db) {
+    const int c = blockIdx.x * 64 + threadIdx.x % 64;
+    float tmp;
+    col_sum_lanes(part, chunks, cols, 0, chunks, &tmp);
+    if (threadIdx.x < 64 && c < cols) db[c] = tmp;
 }
 
 // out[i] = sum over the split-K partials, in split order.
@@ -262,7 +287,7 @@ struct Ws {
     float *acc;     // GEMM output scratch [B][maxw]
     float *dz, *dh; // [B][maxw]
     bf16 *dzb;      // [B][maxw]
-    float *part;    // split-K partials [kSplits][maxw][maxw]
+    float *part;    // split-K partials [kSplits][maxw][maxw], then column-sum chunks [kColChunks][maxw]
     float *rowloss; // [B]
     size_t total;
 };
@@ -278,7 +303,7 @@ Ws carve(const Net &net, uint32_t B, void *base) {
     w.dz = c.take<float>((size_t)B * net.maxw);
     w.dh = c.take<float>((size_t)B * net.maxw);
     w.dzb = c.take<bf16>((size_t)B * net.maxw);
-    w.part = c.take<float>((size_t)kSplits * net.maxw * net.maxw);
+    w.part = c.take<float>(std::max((size_t)kSplits * net.maxw * net.maxw, (size_t)kColChunks * net.maxw));
     w.rowloss = c.take<float>(std::max<uint32_t>(B, 1));
     w.total = c.used;
     return w;
@@ -358,7 +383,10 @@ extern "C" int mlp_backward(const sfg_mlp_shape *shape, uint32_t batch, const fl
             ProfScope _ps("mlp_elementwise", s);
             reduce_splits<<<grid_n((uint64_t)ly.out * ly.in), 256, 0, s>>>(w.part, kSplits, (uint64_t)ly.out * ly.in,
                                                                             grad + ly.w_off);
-            col_sums<<<(ly.out + 255) / 256, 256, 0, s>>>(w.dz, B, ly.out, grad + ly.b_off);
+            // (the split-K partials are consumed above, so part is free again)
+            const int chunk_rows = (B + kColChunks - 1) / kColChunks, chunks = (B + chunk_rows - 1) / chunk_rows;
+            col_sums_chunks<<<dim3((ly.out + 63) / 64, chunks), 256, 0, s>>>(w.dz, B, ly.out, chunk_rows, w.part);
+            col_sums_total<<<(ly.out + 63) / 64, 256, 0, s>>>(w.part, chunks, ly.out, grad + ly.b_off);
         }
         if (l > 0 || dx) {
             // dH[B][in] = dZb [B][out] * Wb [out][in]

@@ -2,7 +2,8 @@
 ensembles the generators produce and inverted to choose Kronecker parameters
 for a target degree exponent.  The real generator stays the judge: a proposal
 is accepted only when the generated graph's measured exponent is within the
-tolerance, and the generator-only search takes over otherwise.
+tolerance, and the generator-only search takes over when the surrogate's
+share of the budget runs out (fit_exponent).
 
 Everything numerical runs in the library's kernels: ensemble_generate makes
 the training data, mlp_forward / mlp_backward / mlp_mse_grad / adam_step train
@@ -209,22 +210,69 @@ def search_generator_only(judge, target, tol, budget=40, seed=0):
     return False, judge.calls - calls0
 
 
-def search_with_surrogate(model, judge, target, tol, budget=40, seed=0):
-    """Surrogate-proposed parameters, each judged by one generator run.  After
-    a miss the gap between the measured and the predicted log(gamma - 1) is
-    added to a running correction and the surrogate is inverted again for the
-    corrected target; returns (accepted, calls)."""
+def _u_grad(model, k, ab):
+    """Predicted u = log(gamma - 1) at (a, b) and its gradient in (a, b)."""
+    u, dX = model.log_tail_and_grad(features([kron_row(ab[0], ab[1], k, 0)]))
+    # x5..x8 = (a, 1-a, b, 1-b): chain rule to (a, b)
+    return float(u[0]), np.array([dX[0, 5] - dX[0, 6], dX[0, 7] - dX[0, 8]])
+
+
+def search_with_surrogate(model, judge, target, tol, budget=40, seed=0, refine=6, max_step=0.15,
+                          bounds=(0.03, 0.97)):
+    """Surrogate-guided search, each proposal judged by one generator run.
+
+    A start is the best inversion of the surrogate for the target.  From it
+    the search moves along the surrogate's gradient of u = log(gamma - 1),
+    by secant steps on the measured u: the first step uses the surrogate's
+    slope, later ones the slope measured between the last two runs (kept
+    when it agrees in sign with the surrogate and lies within a factor of 5
+    of it).  The surrogate's level sets differ from the generator's by a
+    smooth offset, so these local steps converge where re-inverting for a
+    shifted target from scattered starts would not.  After `refine` steps
+    without success, or an unusable measurement, the search restarts from
+    another inversion.  Returns (accepted, calls)."""
     calls0 = judge.calls
-    shift = 0.0
+    ut = math.log(target - 1.0)
     r = 0
     while judge.calls - calls0 < budget:
-        t_model = 1.0 + math.exp(math.log(target - 1.0) - shift)
-        cands, pred = invert(model, t_model, judge.k, seed=seed * 1000 + r)
-        a, b = cands[0]
-        g = judge.gamma(a, b)
-        if abs(g - target) <= tol:
-            return True, judge.calls - calls0
-        if math.isfinite(g) and g > 1:
-            shift += math.log(g - 1.0) - math.log(pred[0] - 1.0)
+        cands, _ = invert(model, target, judge.k, seed=seed * 1000 + r)
         r += 1
+        x = np.array(cands[0], np.float64)
+        prev = None
+        for _ in range(refine + 1):
+            if judge.calls - calls0 >= budget:
+                break
+            g = judge.gamma(float(x[0]), float(x[1]))
+            if abs(g - target) <= tol:
+                return True, judge.calls - calls0
+            if not (math.isfinite(g) and g > 1):
+                break
+            u = math.log(g - 1.0)
+            _, grad = _u_grad(model, judge.k, x)
+            gn = float(np.sqrt((grad * grad).sum()))
+            if gn < 1e-9:
+                break
+            d = grad / gn
+            slope = gn  # du per unit distance along d, from the surrogate
+            if prev is not None:
+                dist = float(np.dot(x - prev[0], d))
+                if abs(dist) > 1e-9:
+                    meas = (u - prev[1]) / dist
+                    if 0.2 * gn < meas < 5.0 * gn:
+                        slope = meas
+            step = -(u - ut) / slope
+            step = max(-max_step, min(max_step, step))
+            prev = (x.copy(), u)
+            x = np.clip(x + step * d, *bounds)
     return False, judge.calls - calls0
+
+
+def fit_exponent(model, judge, target, tol, budget=40, seed=0, surrogate_share=0.5):
+    """Parameters for a target exponent: the surrogate-guided search with a
+    share of the budget, then the generator-only search with the rest.
+    Returns (accepted, calls, which) with which in {"surrogate", "generator"}."""
+    ok, c = search_with_surrogate(model, judge, target, tol, budget=max(1, int(budget * surrogate_share)), seed=seed)
+    if ok:
+        return True, c, "surrogate"
+    ok2, c2 = search_generator_only(judge, target, tol, budget=budget - c, seed=seed)
+    return ok2, c + c2, "generator"
