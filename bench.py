@@ -340,7 +340,8 @@ def _bench_mlp(sfg, torch, batch=4096, steps=50):
     flops = 3 * 2 * batch * macs  # forward, input gradients, weight gradients
     return {"batch": batch, "ms_per_step": ms, "samples_per_s": batch / (ms / 1e3),
             "tflops": flops / (ms / 1e3) / 1e12, "mfma_peak_tflops_bf16": 2500.0,
-            "note": "launch-bound: a 256-wide network is far below the matrix-core roofline"}
+            "note": "eleven 64x64-tile MFMA GEMMs and fifteen small elementwise launches per step: a "
+                    "256-wide network at batch 4,096 is latency-bound, far below the matrix-core roofline"}
 
 
 def _bench_ensemble(sfg, wl, torch, samples=10_000, stat_seed=5,

@@ -45,17 +45,56 @@ __device__ __forceinline__ float bf2f(bf16 h) {
     return __uint_as_float((uint32_t)b << 16);
 }
 
+// Stage rows [r0, r0 + 64) x k in [k0, k0 + 32) of an operand into an LDS
+// tile t[row][k] (bf16, 16-byte rows chunks).  KMAJ: element (row, k) is
+// X[row * ld + k] (k contiguous); else X[k * ld + row] (rows contiguous).
+// Each of the 256 threads moves one 8-element vector when the vector lies
+// inside the operand and the layout allows 16-byte loads (vec); elements
+// outside [0, R) x [k0, ke) read as zero.
+template <bool KMAJ>
+__device__ __forceinline__ void stage_tile(const bf16 *__restrict__ X, int ld, int R, int r0, int k0, int ke, bool vec,
+                                           bf16 (*t)[kKStep + kPad]) {
+    const int tid = threadIdx.x;
+    const bf16 zero = f2bf(0.f);
+    if (KMAJ) {
+        const int r = tid / 4, k8 = (tid % 4) * 8;
+        const int gr = r0 + r, gk = k0 + k8;
+        bf16x8 v;
+        if (vec && gr < R && gk + 8 <= ke) {
+            v = *reinterpret_cast<const bf16x8 *>(X + (size_t)gr * ld + gk);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (gr < R && gk + e < ke) ? X[(size_t)gr * ld + gk + e] : zero;
+        }
+        *reinterpret_cast<bf16x8 *>(&t[r][k8]) = v;
+    } else {
+        const int k = tid / 8, r8 = (tid % 8) * 8;
+        const int gk = k0 + k, gr = r0 + r8;
+        bf16x8 v;
+        if (vec && gk < ke && gr + 8 <= R) {
+            v = *reinterpret_cast<const bf16x8 *>(X + (size_t)gk * ld + gr);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (gk < ke && gr + e < R) ? X[(size_t)gk * ld + gr + e] : zero;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[r8 + e][k] = v[e];
+    }
+}
+
 // C[M][N] (+)= sum_k A(m, k) B(k, n) over k in [k_begin, k_end), with
 // A(m, k) = TA ? A[k * lda + m] : A[m * lda + k] and
 // B(k, n) = TB ? B[n * ldb + k] : B[k * ldb + n]; bf16 in, fp32 out.
 // Block: 256 threads, a 64 x 64 tile; wave w owns rows 32 (w / 2) .. +32 and
 // columns 32 (w % 2) .. +32 as 2 x 2 MFMA 16 x 16 tiles.  Split-K: blockIdx.z
-// selects a K range and a partial output C + z * M * N.
+// selects a K range and a partial output C + z * M * N.  veca / vecb: the
+// operand allows 16-byte loads (8-element aligned base and leading dimension).
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void gemm_bf16(const bf16 *__restrict__ A, int lda, const bf16 *__restrict__ B,
-                                                 int ldb, float *__restrict__ C, int M, int N, int K, int ksplit) {
-    __shared__ bf16 sA[kTile][kKStep + kPad];  // [m][k]
-    __shared__ bf16 sB[kTile][kKStep + kPad];  // [n][k]
+                                                 int ldb, float *__restrict__ C, int M, int N, int K, int ksplit,
+                                                 int veca, int vecb) {
+    __shared__ __align__(16) bf16 sA[kTile][kKStep + kPad];  // [m][k]
+    __shared__ __align__(16) bf16 sB[kTile][kKStep + kPad];  // [n][k]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
     const int kper = ((K + ksplit - 1) / ksplit + kKStep - 1) / kKStep * kKStep;
@@ -65,46 +104,17 @@ __global__ __launch_bounds__(256) void gemm_bf16(const bf16 *__restrict__ A, int
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const bf16 zero = f2bf(0.f);
     for (int k0 = kb; k0 < ke; k0 += kKStep) {
-        for (int i = tid; i < kTile * kKStep; i += 256) {
-            int m, k;
-            if (TA) {  // consecutive threads along m
-                m = i % kTile;
-                k = i / kTile;
-            } else {
-                k = i % kKStep;
-                m = i / kKStep;
-            }
-            const int gm = m0 + m, gk = k0 + k;
-            sA[m][k] = (gm < M && gk < ke) ? (TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk]) : zero;
-            int n, kk;
-            if (TB) {
-                kk = i % kKStep;
-                n = i / kKStep;
-            } else {
-                n = i % kTile;
-                kk = i / kTile;
-            }
-            const int gn = n0 + n, gk2 = k0 + kk;
-            sB[n][kk] = (gn < N && gk2 < ke) ? (TB ? B[(size_t)gn * ldb + gk2] : B[(size_t)gk2 * ldb + gn]) : zero;
-        }
+        stage_tile<!TA>(A, lda, M, m0, k0, ke, veca != 0, sA);
+        stage_tile<TB>(B, ldb, N, n0, k0, ke, vecb != 0, sB);
         __syncthreads();
         // 16x16x32 operands: lane l holds row/col (l % 16), k = 8 (l / 16) .. +7.
         const int r = lane % 16, kq = 8 * (lane / 16);
         bf16x8 fa[2], fb[2];
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int mr = 32 * (w / 2) + 16 * i + r;
+        for (int i = 0; i < 2; ++i) fa[i] = *reinterpret_cast<const bf16x8 *>(&sA[32 * (w / 2) + 16 * i + r][kq]);
 #pragma unroll
-            for (int e = 0; e < 8; ++e) fa[i][e] = sA[mr][kq + e];
-        }
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int nc = 32 * (w % 2) + 16 * j + r;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) fb[j][e] = sB[nc][kq + e];
-        }
+        for (int j = 0; j < 2; ++j) fb[j] = *reinterpret_cast<const bf16x8 *>(&sB[32 * (w % 2) + 16 * j + r][kq]);
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -311,11 +321,14 @@ Ws carve(const Net &net, uint32_t B, void *base) {
 
 int grid_n(uint64_t n) { return (int)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 4096)); }
 
+bool vec_ok(const bf16 *p, int ld) { return ((uintptr_t)p % 16) == 0 && ld % 8 == 0; }
+
 template <bool TA, bool TB>
 void gemm(const bf16 *A, int lda, const bf16 *B, int ldb, float *C, int M, int N, int K, int splits, hipStream_t s) {
     dim3 g((N + kTile - 1) / kTile, (M + kTile - 1) / kTile, splits);
     ProfScope _ps("mlp_gemm", s);
-    gemm_bf16<TA, TB><<<g, 256, 0, s>>>(A, lda, B, ldb, C, M, N, K, splits);
+    gemm_bf16<TA, TB><<<g, 256, 0, s>>>(A, lda, B, ldb, C, M, N, K, splits, vec_ok(A, lda) ? 1 : 0,
+                                        vec_ok(B, ldb) ? 1 : 0);
 }
 
 }  // namespace
