@@ -204,9 +204,10 @@ struct PassArgs {
 template <typename IdT, typename KeyT, bool SYM, bool FIRST, bool BOUND>
 __global__ __launch_bounds__(kPassThreads, BOUND ? 6 : 8) void radix_pass(PassArgs a) {
     // s_keys holds the tile's keys in digit order after ranking; during the
-    // ranking its first 16 KB serve as the per-wave lane-match tables.
+    // ranking its first 32 KB serve as the per-wave lane-match tables.
     __shared__ KeyT s_keys[kPassTile];
-    // 16-bit counters keep the block at about 38 KB of LDS: four tiles per CU.
+    // 16-bit per-wave digit counters (8 KB); with the 64 KB key tile the block takes about 77 KB of LDS
+    // (8-byte keys): two workgroups per CU.
     __shared__ uint16_t s_cnt[kPassWaves][kRadix];
     __shared__ uint16_t s_off[kRadix];
     __shared__ uint16_t s_tot[kRadix];
