@@ -336,9 +336,34 @@ def _bench_mlp(sfg, torch, batch=4096, steps=50):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / steps
+    # The same step captured once into a HIP graph (learning rate and step
+    # counter in device memory) and replayed.
+    y, dy = torch.empty(batch, 34, device="cuda"), torch.empty(batch, 34, device="cuda")
+    loss, grad = torch.empty(1, device="cuda"), torch.empty_like(params)
+    lr_dev = torch.full((1,), 1e-3, device="cuda")
+    step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def gstep():
+        sfg.mlp_forward(shape, params, x, ws, y=y)
+        sfg.mlp_mse_grad(y, t, lws, dy=dy, loss=loss)
+        sfg.mlp_backward(shape, params, dy, ws, grad=grad)
+        sfg.adam_step_device(params, grad, m, v, lr_dev, step_dev)
+
+    gstep()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        gstep()
+    a.record()
+    for _ in range(steps):
+        graph.replay()
+    b.record()
+    torch.cuda.synchronize()
+    ms_graph = a.elapsed_time(b) / steps
+    del graph
     macs = 10 * 256 + 2 * 256 * 256 + 256 * 34
     flops = 3 * 2 * batch * macs  # forward, input gradients, weight gradients
-    return {"batch": batch, "ms_per_step": ms, "samples_per_s": batch / (ms / 1e3),
+    return {"batch": batch, "ms_per_step": ms, "ms_per_step_graph": ms_graph, "samples_per_s": batch / (ms / 1e3),
             "tflops": flops / (ms / 1e3) / 1e12, "mfma_peak_tflops_bf16": 2500.0,
             "note": "eleven 64x64-tile MFMA GEMMs and fifteen small elementwise launches per step: a "
                     "256-wide network at batch 4,096 is latency-bound, far below the matrix-core roofline"}

@@ -76,11 +76,15 @@ int sfg_device_error(void *stream, uint32_t *code);
  * bracketed by a pair of hipEvents recorded on its stream.
  * sfg_profile_query waits for the recorded launches of the kernel called
  * `name` and returns how many there were and their summed duration in
- * milliseconds; sfg_profile_reset forgets all records.  Kernel names:
- * "kron_sample", "kron_enumerate", "csr_prepare", "radix_pass",
- * "csr_finish", "csr_rowfill", "degree_hist", "pba_draw1", "pba_resolve",
- * "pba_count", "pba_scan", "pba_draw2", "pba_substitute", "path_level",
- * "block_count", "random_pairs", "perturb_expand". */
+ * milliseconds; sfg_profile_reset forgets all records.  Launches made while
+ * the stream is being captured into a graph are not timed.  Kernel names:
+ * "kron_sample", "kron_enumerate", "csr_prepare", "csr_digit_bases",
+ * "radix_pass", "csr_finish", "csr_rowfill", "degree_hist", "fill",
+ * "pba_draw1", "pba_resolve", "pba_tile_table", "pba_count", "pba_scan",
+ * "pba_draw2", "pba_substitute", "stats_chunks", "stats_gamma",
+ * "stats_wedge_scan", "stats_wedge", "path_level", "block_count",
+ * "random_pairs", "perturb_expand", "mlp_gemm", "mlp_elementwise",
+ * "mlp_adam". */
 int sfg_profile_enable(int on);
 int sfg_profile_reset(void);
 int sfg_profile_query(const char *name, uint64_t *launches, double *total_ms);
@@ -419,6 +423,15 @@ int mlp_mse_grad(uint32_t batch, uint32_t d_out, const float *y, const float *ta
 /* Adam (Kingma & Ba) with bias correction; step counts from 1. */
 int adam_step(uint64_t count, float *params, const float *grad, float *m, float *v, float lr, float beta1, float beta2,
               float eps, uint32_t step, void *stream);
+
+/* The same update with the learning rate and the step counter in device
+ * memory: the call first increments *step (device uint32, the number of
+ * steps taken so far) and then applies step *step with learning rate *lr
+ * (device float), so that a training step can be captured once into a HIP
+ * graph and replayed while the schedule changes.  Bias corrections use the
+ * device powf, so results may differ in the last bit from adam_step. */
+int adam_step_device(uint64_t count, float *params, const float *grad, float *m, float *v, const float *lr,
+                     float beta1, float beta2, float eps, uint32_t *step, void *stream);
 
 #ifdef __cplusplus
 }

@@ -259,6 +259,24 @@ __global__ void adam_kernel(uint64_t n, float *p, const float *g, float *m, floa
     }
 }
 
+// Device-driven Adam: one thread advances the step counter, then every
+// element reads the step and the learning rate from memory.
+__global__ void adam_tick(uint32_t *step) { *step += 1; }
+
+__global__ void adam_kernel_dev(uint64_t n, float *p, const float *g, float *m, float *v, const float *lr_p,
+                                float b1, float b2, float eps, const uint32_t *step_p) {
+    const float t = (float)*step_p, lr = *lr_p;
+    const float c1 = 1.f - powf(b1, t), c2 = 1.f - powf(b2, t);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
 // ----------------------------------------------------------------------------- host
 struct Layer {
     int in, out;
@@ -433,4 +451,14 @@ extern "C" int adam_step(uint64_t count, float *params, const float *grad, float
     ProfScope _ps("mlp_adam", s);
     adam_kernel<<<grid_n(count), 256, 0, s>>>(count, params, grad, m, v, lr, beta1, beta2, eps, c1, c2);
     return check_launch("adam_step");
+}
+
+extern "C" int adam_step_device(uint64_t count, float *params, const float *grad, float *m, float *v, const float *lr,
+                                float beta1, float beta2, float eps, uint32_t *step, void *stream) {
+    if (!params || !grad || !m || !v || !lr || !step) return fail(SFG_EINVAL, "adam_step_device: NULL buffer");
+    hipStream_t s = as_stream(stream);
+    ProfScope _ps("mlp_adam", s);
+    adam_tick<<<1, 1, 0, s>>>(step);
+    adam_kernel_dev<<<grid_n(count), 256, 0, s>>>(count, params, grad, m, v, lr, beta1, beta2, eps, step);
+    return check_launch("adam_step_device");
 }

@@ -86,9 +86,16 @@ static bool debug_sync() {
     return on;
 }
 
+// Launches recorded into a graph (stream capture) are not timed: an event
+// recorded during capture belongs to the graph, not to a launch.
+static bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(s, &st) == hipSuccess && st != hipStreamCaptureStatusNone;
+}
+
 ProfScope::ProfScope(const char *name, hipStream_t s) : stream(s), kname(name) {
     std::lock_guard<std::mutex> lock(g_prof_mu);
-    if (!g_prof_on) return;
+    if (!g_prof_on || capturing(s)) return;
     if (g_prof_used == g_prof.size()) {
         ProfRecord r{nullptr, nullptr, nullptr, false};
         if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
@@ -101,7 +108,7 @@ ProfScope::ProfScope(const char *name, hipStream_t s) : stream(s), kname(name) {
 }
 
 ProfScope::~ProfScope() {
-    if (debug_sync()) {
+    if (debug_sync() && !capturing(stream)) {
         uint32_t v = 0;
         uint32_t *w = device_error_word();
         if (hipStreamSynchronize(stream) != hipSuccess)

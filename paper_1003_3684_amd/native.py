@@ -61,6 +61,7 @@ SIGNATURES = {
     "mlp_backward": (_i32, [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "mlp_mse_grad": (_i32, [_u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "adam_step": (_i32, [_u64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float, _u32, _vp]),
+    "adam_step_device": (_i32, [_u64, _vp, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, _vp, _vp]),
 }
 
 
@@ -433,6 +434,14 @@ def mlp_mse_grad(y, target, ws, mask=None, col_weight=None, dy=None, loss=None, 
     _check(lib.mlp_mse_grad(B, D, _ptr(y), _ptr(target), _ptr(mask), _ptr(col_weight), _ptr(dy), _ptr(loss), _ptr(ws),
                             ws.numel(), _stream(stream)))
     return dy, loss
+
+
+def adam_step_device(params, grad, m, v, lr_dev, step_dev, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """Adam with the learning rate (float32 [1]) and the step counter (int32
+    [1], incremented by the call) in device memory: capturable into a graph."""
+    assert lr_dev.dtype == torch.float32 and step_dev.dtype == torch.int32
+    _check(load().adam_step_device(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), _ptr(lr_dev), beta1,
+                                   beta2, eps, _ptr(step_dev), _stream(stream)))
 
 
 def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

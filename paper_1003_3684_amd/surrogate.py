@@ -88,8 +88,13 @@ class Surrogate:
         self.mu = np.zeros(D_OUT, np.float32)
         self.sd = np.ones(D_OUT, np.float32)
 
-    def fit(self, X, Y, M, epochs=30, lr=1e-3, seed=0, col_weight=None):
-        """Adam on standardized targets; returns the per-epoch mean loss."""
+    def fit(self, X, Y, M, epochs=30, lr=1e-3, seed=0, col_weight=None, graph=True):
+        """Adam on standardized targets over full batches; returns the
+        per-epoch mean loss.  A training step is: gather the batch, forward,
+        loss gradient, backward, Adam.  The learning rate (cosine schedule)
+        and the step counter live in device memory, so with graph=True the
+        step is captured once into a HIP graph after a first eager step and
+        replayed; the result is bit-identical to the eager loop."""
         rng = np.random.default_rng(seed)
         Mb = M.astype(bool)
         for j in range(D_OUT):
@@ -99,24 +104,52 @@ class Surrogate:
                 self.sd[j] = max(col.std(), 1e-3)
         Ys = (Y - self.mu) / self.sd * M
         cw = torch.tensor(np.ones(D_OUT, np.float32) if col_weight is None else col_weight).cuda()
-        Xg, Yg, Mg = (torch.tensor(a).cuda() for a in (X, Ys.astype(np.float32), M))
+        Xg, Yg, Mg = (torch.tensor(a).cuda() for a in (X, Ys.astype(np.float32), M.astype(np.float32)))
+        N, B = X.shape[0], self.batch
+        nb = N // B
+        if nb == 0:
+            raise ValueError(f"fit needs at least one full batch of {B} rows")
+        dev = self.params.device
+        idx = torch.empty(B, dtype=torch.int64, device=dev)
+        xs = torch.empty((B, D_IN), dtype=torch.float32, device=dev)
+        ys = torch.empty((B, D_OUT), dtype=torch.float32, device=dev)
+        ms = torch.empty((B, D_OUT), dtype=torch.float32, device=dev)
+        y, dy = torch.empty_like(ys), torch.empty_like(ys)
+        loss = torch.empty(1, dtype=torch.float32, device=dev)
+        grad = torch.empty_like(self.params)
+        lr_dev = torch.zeros(1, dtype=torch.float32, device=dev)
+        step_dev = torch.tensor([self.step], dtype=torch.int32, device=dev)
+        loss_acc = torch.zeros(1, dtype=torch.float32, device=dev)
+
+        def step():
+            torch.index_select(Xg, 0, idx, out=xs)
+            torch.index_select(Yg, 0, idx, out=ys)
+            torch.index_select(Mg, 0, idx, out=ms)
+            sfg.mlp_forward(self.shape, self.params, xs, self.ws, y=y)
+            sfg.mlp_mse_grad(y, ys, self.lws, mask=ms, col_weight=cw, dy=dy, loss=loss)
+            sfg.mlp_backward(self.shape, self.params, dy, self.ws, grad=grad)
+            sfg.adam_step_device(self.params, grad, self.m, self.v, lr_dev, step_dev)
+            loss_acc.add_(loss)
+
+        g = None
         history = []
-        N = X.shape[0]
         for ep in range(epochs):
-            order = torch.tensor(rng.permutation(N)).cuda()
-            tot, nb = 0.0, 0
-            lr_ep = lr * 0.5 * (1 + math.cos(math.pi * ep / max(epochs, 1)))
-            for b0 in range(0, N - self.batch + 1, self.batch):
-                idx = order[b0:b0 + self.batch]
-                xb, yb, mb = Xg[idx].contiguous(), Yg[idx].contiguous(), Mg[idx].contiguous()
-                y = sfg.mlp_forward(self.shape, self.params, xb, self.ws)
-                dy, loss = sfg.mlp_mse_grad(y, yb, self.lws, mask=mb, col_weight=cw)
-                grad, _ = sfg.mlp_backward(self.shape, self.params, dy, self.ws)
-                self.step += 1
-                sfg.adam_step(self.params, grad, self.m, self.v, self.step, lr=lr_ep)
-                tot += float(loss.item())
-                nb += 1
-            history.append(tot / max(nb, 1))
+            order = torch.tensor(rng.permutation(N)).to(dev)
+            lr_dev.fill_(lr * 0.5 * (1 + math.cos(math.pi * ep / max(epochs, 1))))
+            loss_acc.zero_()
+            for b in range(nb):
+                idx.copy_(order[b * B:(b + 1) * B])
+                if g is not None:
+                    g.replay()
+                    continue
+                step()
+                if graph:  # every kernel has run once: capture the step
+                    torch.cuda.synchronize()
+                    g = torch.cuda.CUDAGraph()
+                    with torch.cuda.graph(g):
+                        step()
+            history.append(float(loss_acc.item()) / nb)
+        self.step = int(step_dev.item())
         return history
 
     def predict(self, X):
