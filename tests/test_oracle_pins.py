@@ -664,3 +664,124 @@ def test_perturbed_subset_and_expected_size(orc):
     # distinct meta-edges give distinct edges
     s, d = orc.kron_perturbed(seed_m, k, p_add, p_del, 1)
     assert np.unique(s * n + d).size == s.size
+
+
+# ----------------------------------------------------------------------------- PBA brute force
+# Tiny instances whose every outcome is enumerated with its exact probability
+# from the process as the PBA section states it (phase 1: the faction prefix,
+# then an inter-faction draw with probability p or a copy of a uniformly
+# chosen earlier slot; phase 2: preferential attachment grown from a 2-vertex
+# clique, each endpoint a uniform pick from the endpoints so far;
+# substitution in slot order), written here as a probability tree rather
+# than a simulation, against the oracle's outcome frequencies over seeds.
+
+def _exact_p(p):
+    return Fraction(int(math.floor(p * 2 ** 32)), 2 ** 32)  # the Bernoulli threshold over 2^32
+
+
+def _phase1_tree(nslots, q, other, pe):
+    """{labels: probability} for one partition with F(q) = [q] and one
+    non-faction partition `other`."""
+    out = {}
+
+    def rec(lab, pr):
+        j = len(lab)
+        if j == nslots:
+            out[tuple(lab)] = out.get(tuple(lab), 0) + pr
+            return
+        if j == 0:
+            return rec([q], pr)
+        rec(lab + [other], pr * pe)
+        for i in range(j):
+            rec(lab + [lab[i]], pr * (1 - pe) / j)
+
+    rec([], Fraction(1))
+    return out
+
+
+def _phase2_tree(D, L):
+    """{S: probability}: arrival t is local vertex floor(t L / D); its
+    endpoint is one of the 2 + 2t pool entries, uniformly."""
+    out = {}
+
+    def rec(pool, S, pr):
+        t = len(S)
+        if t == D:
+            out[tuple(S)] = out.get(tuple(S), 0) + pr
+            return
+        x = t * L // D
+        for y in pool:
+            rec(pool + [x, y], S + [y], pr / len(pool))
+
+    rec([0, 1], [], Fraction(1))
+    return out
+
+
+def _chi2_against(exact, observed, n):
+    cats = sorted(exact, key=lambda k: -exact[k])
+    exp = np.array([float(exact[c]) * n for c in cats])
+    obs = np.array([observed.get(c, 0) for c in cats], np.float64)
+    assert set(observed) <= set(exact), "an outcome of probability zero occurred"
+    big = exp >= 5
+    e = np.append(exp[big], exp[~big].sum())
+    o = np.append(obs[big], obs[~big].sum())
+    if e[-1] == 0:
+        e, o = e[:-1], o[:-1]
+    return stats.chisquare(o, e).pvalue
+
+
+def test_pba_phase1_brute_force(orc):
+    pe = _exact_p(0.3)
+    exact = _phase1_tree(4, 0, 1, pe)
+    assert sum(exact.values()) == 1
+    n = 30000
+    seen = {}
+    for s in range(n):
+        lab = tuple(int(x) for x in orc.pba_phase1(4, 0, 0.3, [0], [1], s))
+        seen[lab] = seen.get(lab, 0) + 1
+    assert _chi2_against(exact, seen, n) > 1e-3
+
+
+def test_pba_phase2_brute_force(orc):
+    exact = _phase2_tree(4, 3)
+    assert sum(exact.values()) == 1
+    n = 30000
+    seen = {}
+    for s in range(n):
+        S = tuple(int(x) for x in orc.pba_phase2(4, 3, 1, s))
+        seen[S] = seen.get(S, 0) + 1
+    assert _chi2_against(exact, seen, n) > 1e-3
+
+
+def test_pba_whole_graph_brute_force(orc):
+    """P = 2 partitions of L = 2 vertices, m = 1, p = 0.3: the exact law of the
+    whole destination list."""
+    pe = _exact_p(0.3)
+    L, start = 2, [0, 2]
+    exact = {}
+    t0, t1 = _phase1_tree(2, 0, 1, pe), _phase1_tree(2, 1, 0, pe)
+    for (l0, p0), (l1, p1) in product(t0.items(), t1.items()):
+        labels = [list(l0), list(l1)]
+        D = [sum(row.count(l) for row in labels) for l in range(2)]
+        # requester q's share of partition l's list starts after the shares
+        # of the requesters before it (ascending order)
+        off = [[sum(labels[r].count(l) for r in range(q)) for l in range(2)] for q in range(2)]
+        for (S0, a0), (S1, a1) in product(_phase2_tree(D[0], L).items() if D[0] else [((), 1)],
+                                          _phase2_tree(D[1], L).items() if D[1] else [((), 1)]):
+            S = [S0, S1]
+            dst = []
+            for q in range(2):
+                used = [0, 0]
+                for l in labels[q]:
+                    dst.append(start[l] + S[l][off[q][l] + used[l]])
+                    used[l] += 1
+            key = tuple(dst)
+            exact[key] = exact.get(key, 0) + p0 * p1 * a0 * a1
+    assert sum(exact.values()) == 1
+    n = 30000
+    seen = {}
+    for s in range(n):
+        _, dst = orc.pba_generate(4, 1, 2, 0.3, s)
+        key = tuple(int(x) for x in dst)
+        seen[key] = seen.get(key, 0) + 1
+    assert _chi2_against(exact, seen, n) > 1e-3
