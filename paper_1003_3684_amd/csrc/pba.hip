@@ -55,6 +55,20 @@ __host__ __device__ __forceinline__ uint64_t part_start(uint64_t q, uint64_t n, 
     return q * qd + (q * r) / P;
 }
 
+// floor(x / d) by multiply-high with magic = floor((2^32 - 1) / d) (32-bit)
+// or floor((2^64 - 1) / d) (64-bit): the estimate is the quotient or one
+// less, and one correction step makes it exact.
+__device__ __forceinline__ uint32_t div_magic32(uint32_t x, uint32_t d, uint32_t magic) {
+    uint32_t q = __umulhi(x, magic);
+    if (x - q * d >= d) ++q;
+    return q;
+}
+__device__ __forceinline__ uint64_t div_magic64(uint64_t x, uint64_t d, uint64_t magic) {
+    uint64_t q = __umul64hi(x, magic);
+    if (x - q * d >= d) ++q;
+    return q;
+}
+
 // One graph of a batch (device table; a single graph travels by value).
 struct PGraph {
     uint64_t n, vbase, ebase, thr_p, H0;
@@ -162,43 +176,65 @@ struct Draw2Args {
     uint32_t *sel;
 };
 
-__device__ __forceinline__ void pba_draw2_one(const Draw2Args &a, uint64_t gi) {
-    // segment s with sbase[s] <= gi < sbase[s+1]
-    uint32_t lo = 0, hi = a.S;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) / 2;
-        if (a.sbase[mid] <= gi)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    const uint32_t s = lo;
-    uint32_t g;
-    const PGraph &p = a.G.of_seg(s, g);
-    const uint32_t l = s - p.seg0;
-    const uint64_t t = gi - a.sbase[s];
-    const uint64_t D = a.sbase[s + 1] - a.sbase[s];
-    const uint64_t L = part_start(l + 1, p.n, p.P) - part_start(l, p.n, p.P);
-    const Block4 w = philox((uint32_t)t, (uint32_t)(t >> 32), l, p.tag2, p.key0, p.key1);
-    // Pool entry r of the first 2 + 2t: the seed clique (0, 1), an arrival
-    // vertex floor(t' L / D) at even r, or the endpoint of selection t' at odd r.
-    const uint64_t r = uidx64(make_u64(w.w0, w.w1), 2 + 2 * t);
-    uint32_t enc;
-    if (r < 2) {
-        enc = kTerm | (uint32_t)r;
-    } else if ((r & 1) == 0) {
-        const uint64_t tp = (r - 2) >> 1;
-        enc = kTerm | (uint32_t)((tp * L) / D);
-    } else {
-        enc = (uint32_t)((r - 3) >> 1);
-    }
-    a.sel[gi] = enc;
-}
+// Workgroup b draws selections [b C, (b + 1) C) (C = kDrawThreads
+// kDraw2Items) of the concatenated lists: the segment of the first is found
+// once per workgroup, and a thread moves to the next segment only when its
+// selections cross a list boundary.  Per segment the thread keeps L, D and
+// the multiply-high constant for floor(t' L / D).
+constexpr int kDraw2Items = 16;
 
 __global__ __launch_bounds__(kDrawThreads) void pba_draw2(Draw2Args a) {
-    const uint64_t stride = (uint64_t)gridDim.x * kDrawThreads;
-    for (uint64_t gi = (uint64_t)blockIdx.x * kDrawThreads + threadIdx.x; gi < a.total; gi += stride)
-        pba_draw2_one(a, gi);
+    __shared__ uint32_t s_seg;
+    const uint64_t c0 = (uint64_t)blockIdx.x * kDrawThreads * kDraw2Items;
+    if (threadIdx.x == 0) {
+        uint32_t lo = 0, hi = a.S;  // last segment s with sbase[s] <= c0
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) / 2;
+            if (a.sbase[mid] <= c0)
+                lo = mid;
+            else
+                hi = mid;
+        }
+        s_seg = lo;
+    }
+    __syncthreads();
+    uint32_t s = s_seg, g = 0, l = 0;
+    uint64_t b = 0, e = 0, D = 0, L = 0, magic = 0;
+    const PGraph *p = nullptr;
+    bool fresh = true;
+    for (int k = 0; k < kDraw2Items; ++k) {
+        const uint64_t gi = c0 + (uint64_t)k * kDrawThreads + threadIdx.x;
+        if (gi >= a.total) break;
+        while (gi >= a.sbase[s + 1]) {  // list boundary (empty lists are skipped)
+            ++s;
+            fresh = true;
+        }
+        if (fresh) {
+            p = &a.G.of_seg(s, g);
+            l = s - p->seg0;
+            b = a.sbase[s];
+            e = a.sbase[s + 1];
+            D = e - b;
+            L = part_start(l + 1, p->n, p->P) - part_start(l, p->n, p->P);
+            magic = ~0ull / D;
+            fresh = false;
+        }
+        const uint64_t t = gi - b;
+        const Block4 w = philox((uint32_t)t, (uint32_t)(t >> 32), l, p->tag2, p->key0, p->key1);
+        // Pool entry r of the first 2 + 2t: the seed clique (0, 1), an arrival
+        // vertex floor(t' L / D) at even r, or the endpoint of selection t' at odd r.
+        const uint64_t r = uidx64(make_u64(w.w0, w.w1), 2 + 2 * t);
+        uint32_t enc;
+        if (r < 2) {
+            enc = kTerm | (uint32_t)r;
+        } else if ((r & 1) == 0) {
+            const uint64_t tp = (r - 2) >> 1;
+            enc = kTerm | (uint32_t)div_magic64(tp * L, D, magic);
+        } else {
+            enc = (uint32_t)((r - 3) >> 1);
+        }
+        a.sel[gi] = enc;
+    }
 }
 
 // ----------------------------------------------------------------------------- chain resolution
@@ -484,6 +520,12 @@ template <typename IdT, bool MATCH> __global__ __launch_bounds__(kSubThreads) vo
     uint32_t lbits = 0;
     while ((1u << lbits) < P) ++lbits;
     const uint64_t vstart = p.vbase + part_start(q, p.n, p.P);
+    // Per-element divisions by multiply-high: start(l) = l floor(n / P) +
+    // floor(l (n mod P) / P) with l (n mod P) < P^2 <= 2^24, and the local
+    // source j / m with j below the partition's slot count (< 2^31, checked
+    // on the host).
+    const uint64_t pq = p.n / P;
+    const uint32_t pr = (uint32_t)(p.n % P), pmagic = 0xFFFFFFFFu / P, mmagic = 0xFFFFFFFFu / p.m;
     IdT *src = static_cast<IdT *>(a.src), *dst = static_cast<IdT *>(a.dst);
     const uint64_t *lbase = a.sbase + p.seg0;
     for (uint64_t j0 = wfirst; j0 < wlast; j0 += 64) {
@@ -513,8 +555,10 @@ template <typename IdT, bool MATCH> __global__ __launch_bounds__(kSubThreads) vo
         if (valid) {
             const uint64_t y = a.sel[lbase[l] + k + below] & ~kTerm;
             const uint64_t e = b0 + j;
-            src[e] = (IdT)(vstart + j / p.m);
-            dst[e] = (IdT)(p.vbase + part_start(l, p.n, p.P) + y);
+            const uint64_t jm = div_magic32((uint32_t)j, p.m, mmagic);
+            const uint64_t lstart = (uint64_t)l * pq + div_magic32(l * pr, P, pmagic);
+            src[e] = (IdT)(vstart + jm);
+            dst[e] = (IdT)(p.vbase + lstart + y);
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -755,7 +799,7 @@ int pba_run_batch(const PbaGraphSpec *gs, uint32_t count, const uint32_t *factio
 
     // Phase 2.
     Draw2Args d2{G, S, pl.E, sbase, sel};
-    { ProfScope _ps("pba_draw2", s); pba_draw2<<<(unsigned)std::min<uint64_t>((pl.E + kDrawThreads - 1) / kDrawThreads, (uint64_t)cus * 64), kDrawThreads, 0, s>>>(d2); }
+    { ProfScope _ps("pba_draw2", s); pba_draw2<<<(unsigned)((pl.E + kDrawThreads * kDraw2Items - 1) / (kDrawThreads * kDraw2Items)), kDrawThreads, 0, s>>>(d2); }
     { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<kXcd, 1024, 0, s>>>(sbase, S, pl.xstride, xpre, xtot, queues + kXcd); }
     { ProfScope _ps("pba_resolve", s); pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{sel, sbase, xpre, xtot, queues + kXcd, err, S, pl.xstride}); }
 
