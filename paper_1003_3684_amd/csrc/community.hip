@@ -25,11 +25,20 @@ __global__ __launch_bounds__(kCommThreads) void block_count(uint64_t n, uint64_t
         for (uint32_t i = threadIdx.x; i < B * B; i += kCommThreads) s_c[i] = 0;
         __syncthreads();
     }
+    // floor(u B / n) by multiply-high (magic = floor((2^64 - 1) / n); the
+    // estimate is the quotient or one less, one correction step makes it exact).
+    const uint64_t magic = ~0ull / n;
+    auto block_of = [&](uint64_t u) -> uint32_t {
+        const uint64_t x = u * B;
+        uint64_t q = __umul64hi(x, magic);
+        if (x - q * n >= n) ++q;
+        return (uint32_t)q;
+    };
     const uint64_t stride = (uint64_t)gridDim.x * kCommThreads;
     for (uint64_t e = (uint64_t)blockIdx.x * kCommThreads + threadIdx.x; e < E; e += stride) {
         const uint64_t u = (uint64_t)src[e], v = (uint64_t)dst[e];
         if (u >= n || v >= n) continue;  // not a vertex: not counted
-        const uint32_t bi = (uint32_t)(u * B / n), bj = (uint32_t)(v * B / n);
+        const uint32_t bi = block_of(u), bj = block_of(v);
         if (LDS)
             atomicAdd(&s_c[bi * B + bj], 1u);
         else
