@@ -17,7 +17,8 @@ int device_cu_count();
 
 // Launch timing: while profiling is enabled (sfg_profile_enable), a
 // ProfScope around a kernel launch records a pair of hipEvents on the launch
-// stream, and sfg_profile_query sums their durations per kernel name.
+// stream (not while the stream is being captured into a graph), and
+// sfg_profile_query sums their durations per kernel name.
 struct ProfScope {
     ProfScope(const char *name, hipStream_t s);
     ~ProfScope();
@@ -78,8 +79,8 @@ struct Block4 {
     uint32_t w0, w1, w2, w3;
 };
 
-// Three-way XOR in one gfx950 instruction (v_bitop3_b32 with the truth table
-// of a ^ b ^ c); two v_xor_b32 otherwise.
+// Three-way XOR in one gfx950 instruction: v_bitop3_b32 with the truth
+// table of a ^ b ^ c (0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
     return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 }

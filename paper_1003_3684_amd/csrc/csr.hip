@@ -3,13 +3,15 @@
 // Entries (src, dst) are packed into one unsigned key (src << db) | dst, with
 // db = bits(n - 1) (rounded up to a whole digit when in-degrees are needed),
 // and sorted by a least-significant-digit radix sort with 8-bit digits over
-// the live key bits.  Each digit pass is a single
-// "onesweep" kernel: a workgroup takes the next tile by an atomic ticket,
-// ranks its keys stably in LDS, publishes its per-digit counts and finds the
-// counts of all earlier tiles by decoupled look-back, then writes its keys
-// digit run by digit run (coalesced).  One read and one write of every key
-// per pass -- the pass is HBM-bound.  The first pass reads the edge arrays and
-// packs keys on the fly, so no separate packing pass exists.
+// the live key bits.  One histogram pass counts every digit of every pass;
+// each digit pass is then a single "onesweep" kernel: workgroup b takes tile
+// b (8,192 keys; workgroups start in id order, so every tile waited for is
+// already running), ranks its keys stably in LDS, publishes its per-digit
+// counts and finds the counts of all earlier tiles by decoupled look-back,
+// then writes its keys digit run by digit run (coalesced).  One read and one
+// write of every key per pass -- the pass is HBM-bound.  The first pass reads
+// the edge arrays and packs keys on the fly, so no separate packing pass
+// exists.
 //
 // After the sort, one streaming pass writes the columns, marks the first
 // sorted position of every row (its row start) and counts repeated entries;
@@ -188,7 +190,6 @@ struct PassArgs {
     uint64_t *status;       // [tiles][256]
     const uint64_t *gbase;  // [256] of this pass
     const uint64_t *ghist;  // [256] of this pass: digits no entry has skip the look-back
-    uint32_t *ticket;
     uint32_t *err;
     uint64_t *csc;          // column starts (BOUND passes only)
     uint8_t *cmark;         // 1 where a column start was written (BOUND passes only)
@@ -416,7 +417,6 @@ struct FinArgs {
     uint8_t *mark;      // 1 where a row start was written (shared by rp and rp_raw)
     uint64_t *dups;     // [1] accumulated, or null
     uint64_t *status;   // [tiles] look-back words (SIMPLE)
-    uint32_t *ticket;
     uint32_t *err;
     int wb;
 };
@@ -760,7 +760,7 @@ struct Plan {
     uint64_t split;
     uint64_t pass_tiles, fin_tiles, chunks;
     // workspace carving
-    size_t off_keysA, off_keysB, off_status, off_ghist, off_gbase, off_tickets, off_indeg, off_rpraw, off_mark,
+    size_t off_keysA, off_keysB, off_status, off_ghist, off_gbase, off_indeg, off_rpraw, off_mark,
         off_cmark, off_cmin, off_fstatus, total;
 };
 
@@ -800,7 +800,6 @@ Plan make_plan(uint64_t n, uint64_t E, int id_bytes, uint32_t flags, bool want_h
     p.off_status = take(std::max<uint64_t>(p.pass_tiles, 1) * kRadix * 8);
     p.off_ghist = take(8 * kRadix * 8);
     p.off_gbase = take(8 * kRadix * 8);
-    p.off_tickets = take(16 * 4);
     p.off_indeg = take(p.directed_hist ? (n + 1) * 8 : 0);
     p.off_rpraw = take(want_hist && p.simple ? (n + 1) * 8 : 0);
     p.off_mark = take(n + 1);
@@ -845,7 +844,6 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
     uint64_t *status = reinterpret_cast<uint64_t *>(ws + P.off_status);
     uint64_t *ghist = reinterpret_cast<uint64_t *>(ws + P.off_ghist);
     uint64_t *gbase = reinterpret_cast<uint64_t *>(ws + P.off_gbase);
-    uint32_t *tickets = reinterpret_cast<uint32_t *>(ws + P.off_tickets);
     uint64_t *csc = P.directed_hist ? reinterpret_cast<uint64_t *>(ws + P.off_indeg) : nullptr;
     uint64_t *rp_raw_ws = (P.hist && P.simple) ? reinterpret_cast<uint64_t *>(ws + P.off_rpraw) : nullptr;
     uint64_t *cmin = reinterpret_cast<uint64_t *>(ws + P.off_cmin);
@@ -856,7 +854,6 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
     // Clear counters, histograms and look-back words (fill kernels, so the
     // sequence stays valid under stream capture).
     fill<uint64_t>(ghist, 8 * kRadix, 0, s);
-    fill<uint32_t>(tickets, 16, 0, s);
     if (P.N) fill<uint64_t>(status, P.pass_tiles * kRadix, 0, s);
     if (fstatus && P.N) fill<uint64_t>(fstatus, P.fin_tiles, 0, s);
     // Row (and column) starts are written only where a row begins and
@@ -886,7 +883,7 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
             const int remaining = P.passes - 1 - p;  // passes after this one
             KeyT *out = (remaining % 2 == 0) ? keysA : keysB;
             KeyT *in = (remaining % 2 == 0) ? keysB : keysA;
-            PassArgs a{P.E, P.N, src, dst, in, out, status, gbase + p * kRadix, ghist + p * kRadix, tickets + p, err,
+            PassArgs a{P.E, P.N, src, dst, in, out, status, gbase + p * kRadix, ghist + p * kRadix, err,
                        csc, cmark, P.db, 8 * p, (uint32_t)(p + 1), P.tb, P.split, P.n};
             const int g = (int)P.pass_tiles;
             if (csc && p == P.dpasses) {
@@ -900,7 +897,7 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
                 { ProfScope _ps("radix_pass", s); radix_pass<IdT, KeyT, false, false, false><<<g, kPassThreads, 0, s>>>(a); }
             }
         }
-        FinArgs fa{P.N, P.n, keysA, col, row_ptr, P.simple ? rp_raw_ws : nullptr, mark, dups, fstatus, tickets + 15,
+        FinArgs fa{P.N, P.n, keysA, col, row_ptr, P.simple ? rp_raw_ws : nullptr, mark, dups, fstatus,
                    err, P.db};
         if (P.xor_mode)
             { ProfScope _ps("csr_finish", s); csr_finish<IdT, KeyT, true><<<(int)P.fin_tiles, kFinThreads, 0, s>>>(fa); }
