@@ -360,7 +360,13 @@ int block_matrix(uint64_t n, uint64_t num_edges, const void *src, const void *ds
  * workspace.  descs is a host array (read before the call returns; the call
  * waits for its small table uploads).  Kronecker members need n0 <= 4 and
  * n0^k <= 2^32; PBA members use the default factions.
- * workspace: device, ensemble_workspace_bytes(descs, count, max_batch_edges).
+ * workspace: device, ensemble_workspace_bytes(descs, count, max_batch_edges):
+ * with more than one batch that is two halves, and consecutive batches then
+ * alternate between two library streams (default priority), each with its
+ * half, so that one batch's generation overlaps the other's sort; the
+ * caller's stream waits for both before anything it enqueues later.  Any
+ * size from one half up is accepted; below two halves the batches run one
+ * after another on the caller's stream.  Results are the same either way.
  * Errors: EINVAL / ERANGE as the single-graph calls, ENOSPACE.
  * ---------------------------------------------------------------------- */
 enum { SFG_GRAPH_PBA = 0, SFG_GRAPH_KRON = 1 };

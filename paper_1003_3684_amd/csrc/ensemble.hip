@@ -15,6 +15,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "common.hpp"
@@ -307,6 +308,35 @@ int run_batch(const sfg_graph_desc *d, uint32_t b0, uint32_t b1, uint32_t sample
                          gamma, closed, ws + P.off_scratch, s);
 }
 
+// Two library streams per device (default priority) on which consecutive
+// batches alternate, each with its own half of the workspace: one batch's
+// generation (VALU- and latency-bound) overlaps the other's sort
+// (bandwidth-bound).  Results do not depend on the interleaving.
+constexpr int kLanes = 2;
+constexpr int kMaxDevs = 16;
+
+bool lane_streams(hipStream_t out[kLanes]) {
+    static std::mutex mu;
+    static hipStream_t lanes[kMaxDevs][kLanes];
+    static bool made[kMaxDevs];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevs) return false;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!made[dev]) {
+        for (int l = 0; l < kLanes; ++l)
+            if (hipStreamCreateWithFlags(&lanes[dev][l], hipStreamNonBlocking) != hipSuccess) return false;
+        made[dev] = true;
+    }
+    for (int l = 0; l < kLanes; ++l) out[l] = lanes[dev][l];
+    return true;
+}
+
+size_t batch_need(const sfg_graph_desc *descs, const std::vector<std::pair<uint32_t, uint32_t>> &batches) {
+    size_t need = 0;
+    for (auto b : batches) need = std::max(need, plan_batch(descs, b.first, b.second).total);
+    return align256(need);
+}
+
 }  // namespace
 }  // namespace sfg
 
@@ -314,10 +344,9 @@ using namespace sfg;
 
 extern "C" size_t ensemble_workspace_bytes(const sfg_graph_desc *descs, uint32_t count, uint64_t max_batch_edges) {
     if (!descs || count == 0) return 0;
-    size_t need = 0;
-    for (auto b : cut_batches(descs, count, std::max<uint64_t>(max_batch_edges, 1)))
-        need = std::max(need, plan_batch(descs, b.first, b.second).total);
-    return need;
+    const auto batches = cut_batches(descs, count, std::max<uint64_t>(max_batch_edges, 1));
+    // One workspace half per lane (a single batch needs one).
+    return batch_need(descs, batches) * (batches.size() > 1 ? kLanes : 1);
 }
 
 extern "C" int ensemble_generate(const sfg_graph_desc *descs, uint32_t count, uint32_t num_samples,
@@ -337,15 +366,50 @@ extern "C" int ensemble_generate(const sfg_graph_desc *descs, uint32_t count, ui
         }
     }
     const auto batches = cut_batches(descs, count, std::max<uint64_t>(max_batch_edges, 1));
-    size_t need = 0;
-    for (auto b : batches) need = std::max(need, plan_batch(descs, b.first, b.second).total);
+    const size_t need = batch_need(descs, batches);
     if (workspace_bytes < need)
         return fail(SFG_ENOSPACE, "ensemble_generate: workspace has %zu bytes, needs %zu", workspace_bytes, need);
     hipStream_t s = as_stream(stream);
-    for (auto b : batches) {
-        int rc = run_batch(descs, b.first, b.second, num_samples, stat_seed, degree_hist32, gamma, closed,
-                           static_cast<char *>(workspace), workspace_bytes, s);
-        if (rc != SFG_OK) return rc;
+    char *ws = static_cast<char *>(workspace);
+    // With room for two halves, batches alternate between the two lanes;
+    // otherwise they run one after another on the caller's stream.
+    hipStream_t lanes[kLanes];
+    if (batches.size() < 2 || workspace_bytes < kLanes * need || !lane_streams(lanes)) {
+        for (auto b : batches) {
+            int rc = run_batch(descs, b.first, b.second, num_samples, stat_seed, degree_hist32, gamma, closed, ws,
+                               workspace_bytes, s);
+            if (rc != SFG_OK) return rc;
+        }
+        return SFG_OK;
     }
-    return SFG_OK;
+    // Lanes start after the work already on the caller's stream; the caller's
+    // stream continues after both lanes.
+    hipEvent_t start, done[kLanes];
+    if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess)
+        return fail(SFG_EDEVICE, "ensemble_generate: event creation failed");
+    int created = 0;
+    for (; created < kLanes; ++created)
+        if (hipEventCreateWithFlags(&done[created], hipEventDisableTiming) != hipSuccess) break;
+    int rc = created == kLanes ? SFG_OK : fail(SFG_EDEVICE, "ensemble_generate: event creation failed");
+    if (rc == SFG_OK && hipEventRecord(start, s) != hipSuccess) rc = fail(SFG_EDEVICE, "ensemble_generate: event record failed");
+    for (int l = 0; rc == SFG_OK && l < kLanes; ++l)
+        if (hipStreamWaitEvent(lanes[l], start, 0) != hipSuccess) rc = fail(SFG_EDEVICE, "ensemble_generate: stream wait failed");
+    for (size_t i = 0; rc == SFG_OK && i < batches.size(); ++i) {
+        const int l = (int)(i % kLanes);
+        rc = run_batch(descs, batches[i].first, batches[i].second, num_samples, stat_seed, degree_hist32, gamma,
+                       closed, ws + l * need, need, lanes[l]);
+    }
+    // Join the lanes into the caller's stream, also after an error, so that
+    // no lane still runs once the caller reuses the workspace.
+    for (int l = 0; l < created; ++l) {
+        if (hipEventRecord(done[l], lanes[l]) != hipSuccess || hipStreamWaitEvent(s, done[l], 0) != hipSuccess) {
+            (void)hipStreamSynchronize(lanes[l]);
+            if (rc == SFG_OK) rc = fail(SFG_EDEVICE, "ensemble_generate: joining the lanes failed");
+        }
+    }
+    if (rc != SFG_OK)
+        for (int l = 0; l < kLanes; ++l) (void)hipStreamSynchronize(lanes[l]);
+    (void)hipEventDestroy(start);
+    for (int l = 0; l < created; ++l) (void)hipEventDestroy(done[l]);
+    return rc;
 }

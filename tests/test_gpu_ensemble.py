@@ -76,11 +76,23 @@ def test_ensemble_members_match_oracle(sfg, orc):
 
 
 def test_ensemble_workspace_and_errors(sfg):
-    rows = wl.small_ensemble_table(6)
+    """Several batches: the reported size holds two halves, and the batches
+    alternate between two streams; half of it runs them one after another on
+    the caller's stream with the same results; less than half is refused."""
+    import torch
+    rows = wl.small_ensemble_table(24)
     descs = sfg.graph_descs(rows)
-    need_small = sfg.ensemble_workspace_bytes(descs, 1 << 12)
-    need_big = sfg.ensemble_workspace_bytes(descs, 1 << 30)
-    assert 0 < need_small <= need_big
-    ws = sfg.workspace(need_small - 256)
+    need = sfg.ensemble_workspace_bytes(descs, 1 << 14)
+    assert need > 0 and need % 512 == 0
+    outs = []
+    for size in (need, need // 2, need + 4096):
+        out = sfg.ensemble_generate(descs, num_samples=500, stat_seed=3, max_batch_edges=1 << 14,
+                                    ws=sfg.workspace(size))
+        torch.cuda.synchronize()
+        assert sfg.device_error() == 0
+        outs.append([t.cpu().numpy() for t in out])
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            np.testing.assert_array_equal(a, b)
     with pytest.raises(sfg.SfgenError):
-        sfg.ensemble_generate(descs, max_batch_edges=1 << 12, ws=ws)
+        sfg.ensemble_generate(descs, max_batch_edges=1 << 14, ws=sfg.workspace(need // 2 - 256))
