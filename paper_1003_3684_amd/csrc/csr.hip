@@ -88,9 +88,12 @@ __device__ uint64_t block_exclusive_scan_256(uint64_t v, uint64_t *s_tmp /*[4]*/
     return base + x - (tid < 256 ? v : 0);
 }
 
+// (u << wb) | v, with v cut to wb bits: an id outside [0, 2^wb) then changes
+// only its own field, so the key digits always agree with what the histogram
+// pass counts (whichever way it counts them) and no pass writes out of range.
 template <typename IdT, typename KeyT> __device__ __forceinline__ KeyT pack(IdT u, IdT v, int wb) {
     using U = typename std::conditional<sizeof(IdT) == 4, uint32_t, uint64_t>::type;
-    return ((KeyT)(U)u << wb) | (KeyT)(U)v;
+    return ((KeyT)(U)u << wb) | ((KeyT)(U)v & (((KeyT)1 << wb) - 1));
 }
 
 // Key number idx of the (optionally symmetrized) entry sequence.
@@ -118,6 +121,7 @@ struct PrepArgs {
     int wb, passes;    // wb: width of the destination field
     int tb;            // origin bits below the entry (XOR mode)
     uint64_t split;    // first entry of origin 1
+    int dbytes;        // SYM with a whole-byte destination field: its bytes, else 0
 };
 
 template <typename IdT, typename KeyT, bool SYM>
@@ -146,6 +150,17 @@ __global__ __launch_bounds__(256) void csr_prepare(PrepArgs a) {
         for (int u = 0; u < kPrepUnroll; ++u) {
             const uint64_t i = i0 + (uint64_t)u * 256;
             if (i >= a.E) break;
+            if (SYM && a.dbytes) {
+                // Key byte p of (u, v) and of (v, u) together is byte p mod
+                // dbytes of u plus that of v: one count per byte of each end.
+                using U = typename std::conditional<sizeof(IdT) == 4, uint32_t, uint64_t>::type;
+                const uint64_t uu = (U)su[u], vv = (U)du[u];
+                for (int q = 0; q < a.dbytes; ++q) {
+                    atomicAdd(&s_h[(q * kRadix + (uint32_t)((uu >> (8 * q)) & 255)) * kPrepCopies + copy], 1u);
+                    atomicAdd(&s_h[(q * kRadix + (uint32_t)((vv >> (8 * q)) & 255)) * kPrepCopies + copy], 1u);
+                }
+                continue;
+            }
             KeyT k = pack<IdT, KeyT>(su[u], du[u], a.wb);
             if (a.tb) k = (KeyT)((k << 1) | (KeyT)(i >= a.split ? 1u : 0u));
             for (int p = 0; p < a.passes; ++p)
@@ -159,9 +174,11 @@ __global__ __launch_bounds__(256) void csr_prepare(PrepArgs a) {
     }
     __syncthreads();
     for (int i = threadIdx.x; i < a.passes * kRadix; i += 256) {
+        // (with dbytes, pass p's histogram is the byte histogram p mod dbytes)
+        const int row = (SYM && a.dbytes) ? (i / kRadix) % a.dbytes * kRadix + i % kRadix : i;
         uint32_t t = 0;
 #pragma unroll
-        for (int c = 0; c < kPrepCopies; ++c) t += s_h[i * kPrepCopies + c];
+        for (int c = 0; c < kPrepCopies; ++c) t += s_h[row * kPrepCopies + c];
         if (t) atomicAdd((unsigned long long *)&a.ghist[i], (unsigned long long)t);
     }
 }
@@ -782,6 +799,13 @@ Plan make_plan(uint64_t n, uint64_t E, int id_bytes, uint32_t flags, bool want_h
     // With in-degrees wanted, the destination field fills whole digits so
     // that some pass boundary leaves the keys ordered by destination.
     p.db = p.directed_hist ? 8 * ((p.wb + 7) / 8) : p.wb;
+    // Symmetrized: a whole-byte destination field lets the histogram pass
+    // count bytes of the two endpoints instead of every digit of both keys;
+    // taken when it costs no pass and no key width.
+    if (p.sym && !xor_mode) {
+        const int db8 = 8 * ((p.wb + 7) / 8);
+        if ((p.wb + db8 + 7) / 8 == (2 * p.wb + 7) / 8 && (p.wb + db8 <= 32) == (2 * p.wb <= 32)) p.db = db8;
+    }
     p.dpasses = p.db / 8;
     p.kb = p.wb + p.db + p.tb;
     p.passes = (p.kb + 7) / 8;
@@ -868,7 +892,8 @@ int run_csr(const Plan &P, const void *src, const void *dst, uint64_t *row_ptr, 
     if (hist) fill<uint64_t>(hist, 32, 0, s);
 
     if (P.N > 0) {
-        PrepArgs pa{P.E, P.N, src, dst, ghist, P.db, P.passes, P.tb, P.split};
+        PrepArgs pa{P.E, P.N, src, dst, ghist, P.db, P.passes, P.tb, P.split,
+                    (P.sym && !P.xor_mode && P.db % 8 == 0) ? P.db / 8 : 0};
         // Every histogram workgroup stays resident (32 KB of LDS each).
         const int pg = (int)std::max<uint64_t>(1, std::min<uint64_t>((P.E + 255) / 256,
                                                                       (uint64_t)device_cu_count() * kPrepBlocksPerCu));
