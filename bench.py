@@ -57,6 +57,48 @@ def _traffic_from_profile(kernel_hash):
         return None
 
 
+def _valu_per_edge_from_profile():
+    """VALU wave-instructions per edge of the Kronecker sampler from the
+    committed rocprofv3 SQ-counter summary, or None if it was taken on a
+    different sampler source."""
+    h = hashlib.sha256()
+    for f in ("kron.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1003_3684_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    path = os.path.join(ROOT, "profiles", "kron_sample_kron_scale_valu.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256_16") != h.hexdigest()[:16]:
+        return None
+    try:
+        return float(vals["valu_instructions_per_edge"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _host_info():
+    """CPU model, usable cores and RAM of the host the CPU baseline ran on."""
+    model, ram = "unknown", None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                ram = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"cpu": model, "usable_cores": cores, "ram_gib": ram}
+
+
 def _cpu_baseline(cfg, sample_edges):
     """The oracle on the first `sample_edges` edges of the workload: sampling
     plus CSR of that sample, single-threaded; scaled to edges/s."""
@@ -70,7 +112,8 @@ def _cpu_baseline(cfg, sample_edges):
     t2 = time.perf_counter()
     return {"value": sample_edges / (t2 - t0), "unit": "edges/s", "cores": 1, "kind": "oracle",
             "sample": f"first {sample_edges} edges of the workload: oracle Kronecker sampling ({t1 - t0:.1f} s) "
-                      f"+ CSR sort and degree histogram ({t2 - t1:.1f} s), single thread"}
+                      f"+ CSR sort and degree histogram ({t2 - t1:.1f} s), single thread",
+            "host": _host_info()}
 
 
 def main():
@@ -78,7 +121,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-sample", type=int, default=1 << 24, help="edges in the CPU-oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=1 << 25, help="edges in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the PBA and ensemble extras")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -166,6 +209,15 @@ def main():
     traffic = _traffic_from_profile(_kernel_source_hash())
     gen_ms = kernels["kron_sample"]["ms_per_step"]
     total_kernel_ms = sum(v["ms_per_step"] for v in kernels.values())
+    # The sampler is bound by VALU issue: 256 CUs x 4 SIMDs x 2.4 GHz / 4
+    # cycles per wave64 instruction; its instruction count per edge comes from
+    # the committed SQ-counter profile (null when the source has changed).
+    valu_peak = 256 * 4 * 2.4e9 / 4
+    vpe = _valu_per_edge_from_profile()
+    generation = {"edges_per_s": E / (gen_ms / 1e3), "write_GBs": 16 * E / (gen_ms / 1e3) / 1e9, "bound": "alu",
+                  "valu_instr_per_edge": vpe,
+                  "alu_frac": None if vpe is None else vpe * E / 64 / (gen_ms / 1e3) / valu_peak,
+                  "alu_peak_wave_instr_per_s": valu_peak}
     result = {
         "metric": "edges/s + achieved HBM GB/s at 1B-vertex scale; batched vs plain graphs/s",
         "value": edges_per_s,
@@ -186,8 +238,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "radix_pass",
                      "algorithmic_bytes_per_step": radix_bytes, "launches_per_step": passes},
         "kernels": kernels,
-        "generation": {"edges_per_s": E / (gen_ms / 1e3), "write_GBs": 16 * E / (gen_ms / 1e3) / 1e9,
-                       "bound": "alu"},
+        "generation": generation,
         "csr_edges_per_s": E / ((total_kernel_ms - gen_ms) / 1e3),
     }
     del src, dst, row_ptr, col, ws
