@@ -5,7 +5,9 @@ A step is one pass of the hot path over the 1-billion-vertex-scale Kronecker
 workload: sample 5 x 2^30 edges from a 3x3 initiator zero-padded to 4x4 with
 15 levels (2^30 vertex ids, int64 endpoints, ~80 GB edge list), then sort them
 into compressed sparse rows with the repeated-edge count and the 32-bin degree
-histogram.  Inputs are synthetic and produced on the GPU by the generator
+histogram -- one library call (kron_generate_csr), in which the sampler also
+counts the sort's digit histogram.  The same step as two calls (kron_generate,
+then edges_to_csr with its own histogram pass) is timed beside it.  Inputs are synthetic and produced on the GPU by the generator
 itself; every buffer is resident in HBM before the timed region starts.
 
 One JSON line is printed.  Besides the headline edges/s it carries the
@@ -169,6 +171,15 @@ def main():
     sptr = C.c_void_p(stream.cuda_stream)
 
     def step():
+        # One call: the sampler writes the edge list and counts the sort's
+        # digit histogram; the CSR build follows on the same stream.
+        rc = lib.kron_generate_csr(n0, wptr, k, E, 0, seed, 0, 8, C.c_void_p(src.data_ptr()),
+                                   C.c_void_p(dst.data_ptr()), flags, C.c_void_p(row_ptr.data_ptr()),
+                                   C.c_void_p(col.data_ptr()), C.c_void_p(hist.data_ptr()),
+                                   C.c_void_p(dups.data_ptr()), C.c_void_p(ws.data_ptr()), ws.numel(), sptr)
+        assert rc == 0, lib.sfg_last_error()
+
+    def two_call_step():
         rc = lib.kron_generate(n0, wptr, k, E, 0, seed, 0, 8, C.c_void_p(src.data_ptr()),
                                C.c_void_p(dst.data_ptr()), sptr)
         assert rc == 0, lib.sfg_last_error()
@@ -193,6 +204,7 @@ def main():
     assert sfg.device_error() == 0
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     edges_per_s = E / (ms_per_step / 1e3)
+    fused_hist = hist.clone()
 
     kernels = {}
     for name in ("kron_sample", "csr_prepare", "radix_pass", "csr_finish", "csr_rowfill", "degree_hist", "fill",
@@ -241,6 +253,19 @@ def main():
         "generation": generation,
         "csr_edges_per_s": E / ((total_kernel_ms - gen_ms) / 1e3),
     }
+    if not args.no_extras:
+        # The same step as two library calls (kron_generate, then edges_to_csr
+        # with its own histogram pass over the edge list), for comparison.
+        two_call_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            two_call_step()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        assert sfg.device_error() == 0
+        result["two_call_step"] = {"ms_per_step": (t1 - t0) * 1e3 / 3,
+                                   "degree_hist_identical": bool(torch.equal(hist, fused_hist))}
     del src, dst, row_ptr, col, ws
     torch.cuda.empty_cache()
 

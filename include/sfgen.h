@@ -213,6 +213,36 @@ int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *ds
                  void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
+ * kron_generate_csr -- a Kronecker graph and its CSR in one call (the PK
+ * method's generation, section "Parallel Kronecker (PK) method", followed by
+ * the adjacency build of the Results section's analyses).
+ *
+ * Equivalent to kron_generate(n0, initiator, k, num_edges, mode, seed,
+ * graph_id, id_bytes, src, dst, stream) followed by edges_to_csr(n0^k,
+ * num_edges, src, dst, id_bytes, flags, row_ptr, col, degree_hist32,
+ * num_duplicates, workspace, workspace_bytes, stream): every output, src and
+ * dst included, is bit-identical to that pair's.  The difference is where the
+ * sort's digit histogram is counted: when the CSR key's digits are whole
+ * bytes of the ids (always with degree_hist32, else when bits(n0^k - 1) is a
+ * multiple of 8; symmetrized, when edges_to_csr takes its whole-byte
+ * destination field) and the sampler is the register path (sample mode, at
+ * most 15 distinct initiator thresholds), the sampler counts the bytes of
+ * the ids it writes, and the pass that would read the edge list back to
+ * count them is skipped.  Otherwise the call runs the two steps unchanged.
+ *
+ * Arguments: those of kron_generate and edges_to_csr, with n = n0^k, which
+ * must not exceed 2^32.  src and dst are outputs here (device, num_edges ids
+ * each); the workspace is edges_to_csr_workspace_bytes(n0^k, num_edges,
+ * id_bytes, flags) bytes and must not overlap src, dst or the outputs.
+ * Errors: those of both calls; when one is returned, src, dst and the CSR
+ * outputs are left untouched.
+ * ---------------------------------------------------------------------- */
+int kron_generate_csr(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges, int mode, uint64_t seed,
+                      uint32_t graph_id, int id_bytes, void *src, void *dst, uint32_t flags, uint64_t *row_ptr,
+                      void *col, uint64_t *degree_hist32, uint64_t *num_duplicates, void *workspace,
+                      size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
  * graph_stats -- statistics of one edge list, as the paper characterises its
  * graphs (Results: degree distributions with fitted exponents, Fig. 3).
  *

@@ -85,7 +85,13 @@ struct FastArgs {
     uint32_t n0, shift;
     uint32_t tm1[15];
     uint64_t lut_row, lut_col;
+    // Byte counting (ByteCount): LDS rows, flushed into hist at the end.
+    uint64_t *hist;
+    int rows, row_mod, dst_row, dst_bytes, src_row, src_bytes;
 };
+
+constexpr int kCountRows = 8;    // byte-count rows a sampler workgroup keeps in LDS
+constexpr int kCountCopies = 4;  // interleaved copies of every counter
 
 template <int NT> __device__ __forceinline__ uint32_t bucket_of(uint32_t w, const uint32_t (&t)[15]) {
     uint32_t b = 0;
@@ -105,11 +111,22 @@ constexpr int kGuideBits = 13;
 constexpr uint32_t kGuideSize = 1u << kGuideBits;
 constexpr uint32_t kStraddle = 0x80;
 
-template <typename IdT, typename AccT, bool POW2, int NT>
+// With CNT the kernel also counts the bytes of the ids it writes (ByteCount in
+// kron.hpp): one LDS row of 256 counters per counted byte position, added
+// into the global rows once per workgroup.  The counts are exact integers, so
+// the result does not depend on the order in which lanes add them.
+template <typename IdT, typename AccT, bool POW2, int NT, bool CNT>
 __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__restrict__ src, IdT *__restrict__ dst) {
     // With few thresholds the comparisons are cheaper than the table.
     constexpr bool kGuide = NT > 3;
     __shared__ uint8_t s_guide[kGuide ? 2 * kGuideSize : 1];  // row digits | kStraddle, then column digits
+    // Lane l counts in copy l mod kCountCopies: lanes of a wave that draw the
+    // same byte (frequent for skewed initiators) would otherwise serialise
+    // their LDS atomics on one address.
+    __shared__ uint32_t s_cnt[CNT ? kCountRows * 256 * kCountCopies : 1];
+    const uint32_t copy = threadIdx.x % kCountCopies;
+    if (CNT)
+        for (uint32_t i = threadIdx.x; i < kCountRows * 256 * kCountCopies; i += kBlock) s_cnt[i] = 0;
     if (kGuide) {
         for (uint32_t i = threadIdx.x; i < kGuideSize; i += kBlock) {
             const uint32_t lo = i << (32 - kGuideBits), hi = lo | ((1u << (32 - kGuideBits)) - 1u);
@@ -118,8 +135,8 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
             s_guide[i] = (uint8_t)(rd | (blo == bhi ? 0u : kStraddle));
             s_guide[kGuideSize + i] = (uint8_t)cd;
         }
-        __syncthreads();
     }
+    if (kGuide || CNT) __syncthreads();
     // Levels 4 blk .. 4 blk + nlev - 1 of edge (elo, ehi) from Philox block blk.
     auto levels = [&](uint32_t elo, uint32_t ehi, uint32_t blk, uint32_t nlev, AccT &u, AccT &v) {
         const Block4 r = philox(elo, ehi, blk, a.tagword, a.key0, a.key1);
@@ -166,6 +183,25 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
         if (rest) levels(elo, ehi, full, rest, u, v);
         src[i] = (IdT)u;
         dst[i] = (IdT)v;
+        if (CNT) {
+#pragma unroll
+            for (int q = 0; q < (int)sizeof(AccT); ++q) {
+                if (q < a.dst_bytes)
+                    atomicAdd(&s_cnt[((a.dst_row + q) * 256 + (uint32_t)((v >> (8 * q)) & 255u)) * kCountCopies + copy], 1u);
+                if (q < a.src_bytes)
+                    atomicAdd(&s_cnt[((a.src_row + q) * 256 + (uint32_t)((u >> (8 * q)) & 255u)) * kCountCopies + copy], 1u);
+            }
+        }
+    }
+    if (CNT) {
+        __syncthreads();
+        for (uint32_t i = threadIdx.x; i < (uint32_t)a.rows * 256; i += kBlock) {
+            const uint32_t slot = ((i >> 8) % (uint32_t)a.row_mod) * 256 + (i & 255u);
+            uint32_t t = 0;
+#pragma unroll
+            for (int c = 0; c < kCountCopies; ++c) t += s_cnt[slot * kCountCopies + c];
+            if (t) atomicAdd((unsigned long long *)&a.hist[i], (unsigned long long)t);
+        }
     }
 }
 
@@ -315,24 +351,41 @@ int grid_for(uint64_t items) {
     return (int)std::max<uint64_t>(1, std::min(want, cap));
 }
 
-template <typename IdT, typename AccT, bool POW2>
+template <typename IdT, typename AccT, bool POW2, bool CNT>
 void launch_fast(const FastArgs &a, uint32_t nt, void *src, void *dst, hipStream_t s) {
     const int g = grid_for(a.num_edges);
     IdT *S = static_cast<IdT *>(src), *D = static_cast<IdT *>(dst);
     if (nt <= 3)
-        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 3><<<g, kBlock, 0, s>>>(a, S, D); }
+        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 3, CNT><<<g, kBlock, 0, s>>>(a, S, D); }
     else if (nt <= 8)
-        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 8><<<g, kBlock, 0, s>>>(a, S, D); }
+        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 8, CNT><<<g, kBlock, 0, s>>>(a, S, D); }
     else
-        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 15><<<g, kBlock, 0, s>>>(a, S, D); }
+        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 15, CNT><<<g, kBlock, 0, s>>>(a, S, D); }
 }
 
 template <typename IdT, typename AccT>
-void launch_fast_any(const FastArgs &a, bool pow2, uint32_t nt, void *src, void *dst, hipStream_t s) {
-    if (pow2)
-        launch_fast<IdT, AccT, true>(a, nt, src, dst, s);
+void launch_fast_any(const FastArgs &a, bool pow2, bool cnt, uint32_t nt, void *src, void *dst, hipStream_t s) {
+    if (pow2 && cnt)
+        launch_fast<IdT, AccT, true, true>(a, nt, src, dst, s);
+    else if (pow2)
+        launch_fast<IdT, AccT, true, false>(a, nt, src, dst, s);
+    else if (cnt)
+        launch_fast<IdT, AccT, false, true>(a, nt, src, dst, s);
     else
-        launch_fast<IdT, AccT, false>(a, nt, src, dst, s);
+        launch_fast<IdT, AccT, false, false>(a, nt, src, dst, s);
+}
+
+// Whether a ByteCount request is one the register path can take: rows inside
+// the LDS table, and per-workgroup counts that fit 32 bits.
+bool count_ok(const ByteCount &bc, uint64_t count, int id_bytes) {
+    if (!bc.hist || bc.rows < 1 || bc.rows > kCountRows || bc.row_mod < 1 || bc.row_mod > bc.rows) return false;
+    if (bc.dst_bytes < 0 || bc.src_bytes < 0 || bc.dst_bytes > id_bytes || bc.src_bytes > id_bytes) return false;
+    if (bc.dst_row < 0 || bc.src_row < 0 || bc.dst_row + bc.dst_bytes > kCountRows ||
+        bc.src_row + bc.src_bytes > kCountRows)
+        return false;
+    const uint64_t threads = (uint64_t)grid_for(count) * kBlock;
+    const uint64_t per_group = (count + threads - 1) / threads * kBlock;
+    return 2 * per_group < (1ull << 32);
 }
 
 }  // namespace
@@ -349,6 +402,16 @@ extern "C" int kron_generate(uint32_t n0, const float *initiator, uint32_t k, ui
 extern "C" int kron_generate_range(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges,
                                    uint64_t e_begin, uint64_t count, int mode, uint64_t seed, uint32_t graph_id,
                                    int id_bytes, void *src, void *dst, void *stream) {
+    return sfg::kron_generate_counted(n0, initiator, k, num_edges, e_begin, count, mode, seed, graph_id, id_bytes, src,
+                                      dst, as_stream(stream), nullptr, nullptr);
+}
+
+namespace sfg {
+
+int kron_generate_counted(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges, uint64_t e_begin,
+                          uint64_t count, int mode, uint64_t seed, uint32_t graph_id, int id_bytes, void *src,
+                          void *dst, hipStream_t s, const ByteCount *bc, bool *counted) {
+    if (counted) *counted = false;
     if (n0 < 2) return fail(SFG_EINVAL, "kron_generate: n0 must be >= 2 (got %u)", n0);
     if (k == 0) return fail(SFG_EINVAL, "kron_generate: k must be >= 1");
     if (!initiator) return fail(SFG_EINVAL, "kron_generate: initiator is NULL");
@@ -368,7 +431,6 @@ extern "C" int kron_generate_range(uint32_t n0, const float *initiator, uint32_t
     const bool pow2 = (n0 & (n0 - 1)) == 0;
     uint32_t shift = 0;
     while ((1u << shift) < n0) ++shift;
-    hipStream_t s = as_stream(stream);
 
     if (mode == SFG_KRON_ENUMERATE) {
         if (n0 > 64) return fail(SFG_EINVAL, "kron_generate: enumerate mode needs n0 <= 64");
@@ -443,12 +505,23 @@ extern "C" int kron_generate_range(uint32_t n0, const float *initiator, uint32_t
             a.lut_row |= (uint64_t)tab.row[b] << (4 * b);
             a.lut_col |= (uint64_t)tab.col[b] << (4 * b);
         }
+        const bool cnt = bc && count_ok(*bc, count, id_bytes);
+        if (cnt) {
+            a.hist = bc->hist;
+            a.rows = bc->rows;
+            a.row_mod = bc->row_mod;
+            a.dst_row = bc->dst_row;
+            a.dst_bytes = bc->dst_bytes;
+            a.src_row = bc->src_row;
+            a.src_bytes = bc->src_bytes;
+        }
         if (id_bytes == 4)
-            launch_fast_any<int32_t, uint32_t>(a, pow2, tab.nt, src, dst, s);
+            launch_fast_any<int32_t, uint32_t>(a, pow2, cnt, tab.nt, src, dst, s);
         else if (acc32)
-            launch_fast_any<int64_t, uint32_t>(a, pow2, tab.nt, src, dst, s);
+            launch_fast_any<int64_t, uint32_t>(a, pow2, cnt, tab.nt, src, dst, s);
         else
-            launch_fast_any<int64_t, uint64_t>(a, pow2, tab.nt, src, dst, s);
+            launch_fast_any<int64_t, uint64_t>(a, pow2, cnt, tab.nt, src, dst, s);
+        if (counted) *counted = cnt;
         return check_launch("kron_generate(sample)");
     }
     GeneralArgs a;
@@ -469,3 +542,5 @@ extern "C" int kron_generate_range(uint32_t n0, const float *initiator, uint32_t
         { ProfScope _ps("kron_sample", s); kron_sample_general<int64_t, uint64_t><<<g, kBlock, 0, s>>>(a, tab, (int64_t *)src, (int64_t *)dst); }
     return check_launch("kron_generate(sample, general)");
 }
+
+}  // namespace sfg

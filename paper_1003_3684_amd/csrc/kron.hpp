@@ -2,6 +2,7 @@
 // generator.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace sfg {
@@ -18,5 +19,24 @@ struct SampleTable {
 // Binary64 thresholds floor(S_c / T * 2^32) of a float32 initiator (n0 x n0,
 // row-major); returns SFG_EINVAL for a negative, non-finite or zero matrix.
 int build_sample_table(uint32_t n0, const float *W, SampleTable &tab);
+
+// Byte counts that a sampler launch can add while it writes the ids, in place
+// of a later pass that reads the edge list to count them: byte q of every
+// destination id is counted in row dst_row + q (q < dst_bytes), byte q of
+// every source id in row src_row + q (q < src_bytes); at the end
+// hist[r * 256 + value] (uint64) gains the count of row r mod row_mod, for
+// every r < rows (rows <= 8).
+struct ByteCount {
+    uint64_t *hist;
+    int rows, row_mod;
+    int dst_row, dst_bytes, src_row, src_bytes;
+};
+
+// kron_generate_range with an optional ByteCount.  *counted tells whether the
+// launch counted; the register-path sampler (sample mode, at most 15
+// distinct thresholds) does, the other paths leave hist untouched.
+int kron_generate_counted(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges, uint64_t e_begin,
+                          uint64_t count, int mode, uint64_t seed, uint32_t graph_id, int id_bytes, void *src,
+                          void *dst, hipStream_t s, const ByteCount *bc, bool *counted);
 
 }  // namespace sfg

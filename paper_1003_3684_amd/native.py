@@ -44,6 +44,8 @@ SIGNATURES = {
     "pba_generate": (_i32, [_u64, _u32, _u32, _dbl, _vp, _vp, _u64, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "edges_to_csr_workspace_bytes": (_sz, [_u64, _u64, _i32, _u32]),
     "edges_to_csr": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "kron_generate_csr": (_i32, [_u32, _vp, _u32, _u64, _i32, _u64, _u32, _i32, _vp, _vp, _u32, _vp, _vp, _vp, _vp,
+                                 _vp, _sz, _vp]),
     "graph_stats_workspace_bytes": (_sz, [_u64, _u64, _i32]),
     "graph_stats": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _u64, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "path_stats_workspace_bytes": (_sz, [_u64]),
@@ -249,6 +251,40 @@ def edges_to_csr(n, src, dst, *, flags=0, want_hist=True, want_dups=True, row_pt
     _check(lib.edges_to_csr(n, E, _ptr(src), _ptr(dst), id_bytes, flags, _ptr(row_ptr), _ptr(col), _ptr(hist),
                             _ptr(dups), _ptr(ws), ws.numel(), _stream(stream)))
     return row_ptr, col, hist, dups
+
+
+def kron_generate_csr(n0, initiator, k, num_edges, *, mode=KRON_SAMPLE, seed=0, graph_id=0, id_bytes=4, flags=0,
+                      want_hist=True, want_dups=True, src=None, dst=None, row_ptr=None, col=None, ws=None,
+                      stream=None):
+    """kron_generate followed by edges_to_csr in one library call (the sampler
+    counts the sort's digit histogram): returns (src, dst, row_ptr, col,
+    hist32 or None, dups tensor or None)."""
+    _require_cuda()
+    lib = load()
+    W = torch.as_tensor(initiator, dtype=torch.float32).contiguous().reshape(-1)
+    if W.numel() != n0 * n0:
+        raise ValueError("initiator must have n0*n0 entries")
+    n = n0 ** k
+    if n > 1 << 32:
+        raise ValueError(f"{n0}^{k} vertices exceed 2^32")
+    dt = _idtype(id_bytes)
+    N = 2 * num_edges if flags & CSR_SYMMETRIZE else num_edges
+    if src is None:
+        src = torch.empty(num_edges, dtype=dt, device="cuda")
+    if dst is None:
+        dst = torch.empty(num_edges, dtype=dt, device="cuda")
+    if row_ptr is None:
+        row_ptr = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    if col is None:
+        col = torch.empty(max(N, 1), dtype=dt, device="cuda")
+    hist = torch.empty(32, dtype=torch.int64, device="cuda") if want_hist else None
+    dups = torch.empty(1, dtype=torch.int64, device="cuda") if want_dups else None
+    if ws is None:
+        ws = workspace(edges_to_csr_workspace_bytes(n, num_edges, id_bytes, flags))
+    _check(lib.kron_generate_csr(n0, C.c_void_p(W.data_ptr()), k, num_edges, mode, seed, graph_id, id_bytes,
+                                 _ptr(src), _ptr(dst), flags, _ptr(row_ptr), _ptr(col), _ptr(hist), _ptr(dups),
+                                 _ptr(ws), ws.numel(), _stream(stream)))
+    return src, dst, row_ptr, col, hist, dups
 
 
 # ----------------------------------------------------------------------------- statistics

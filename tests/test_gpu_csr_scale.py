@@ -3,8 +3,10 @@ on the GPU by invariants that pin the CSR exactly (no CPU sort of billions
 of entries is needed):
 
 * the benchmark step: 5 x 2^30 Kronecker edges (3x3 initiator padded to
-  4x4, 15 levels, int64 ids), directed CSR with duplicate count and degree
-  histogram: row starts are the exclusive scan of the source counts, every
+  4x4, 15 levels, int64 ids) generated and sorted by the one-call
+  kron_generate_csr (the sampler counts the sort's histogram), directed CSR
+  with duplicate count and degree histogram: sampled edges equal the
+  oracle's, row starts are the exclusive scan of the source counts, every
   row is sorted, the multiset of (row, column) equals that of (src, dst)
   (64-bit sum of a mixing function of the packed pair), the duplicate count
   equals the repeated sorted positions, and the histogram equals the one of
@@ -70,17 +72,35 @@ def _row_starts_mask(rp, n, total):
     return starts
 
 
+def _sampled_edges(orc, c, src, dst, chunk=4096, n_random=500):
+    """Chunks at the start, across 2^32 and at the ragged end, and random
+    single edges, each equal to the oracle's."""
+    import torch
+    E = c["num_edges"]
+    for s in (0, (1 << 32) - chunk // 2, E - chunk):
+        os_, od = orc.kron_sample(c["n0"], c["initiator"], c["k"], chunk, c["seed"], 0, e_begin=s)
+        np.testing.assert_array_equal(src[s:s + chunk].cpu().numpy(), os_)
+        np.testing.assert_array_equal(dst[s:s + chunk].cpu().numpy(), od)
+    idx = np.sort(np.random.default_rng(c["seed"] + 1).integers(0, E, size=n_random))
+    gi = torch.as_tensor(idx, device="cuda")
+    gs, gd = src[gi].cpu().numpy(), dst[gi].cpu().numpy()
+    for j, e in enumerate(idx):
+        os_, od = orc.kron_sample(c["n0"], c["initiator"], c["k"], 1, c["seed"], 0, e_begin=int(e))
+        assert gs[j] == os_[0] and gd[j] == od[0], int(e)
+
+
 @pytest.mark.timeout(900)
-def test_bench_csr_at_full_size(sfg):
+def test_bench_csr_at_full_size(sfg, orc):
     import torch
     c = wl.KRON_SCALE
     n, E = c["n0"] ** c["k"], c["num_edges"]
     print(f"case {c['name']}: n={n} E={E}", flush=True)
-    src, dst = sfg.kron_generate(c["n0"], c["initiator"], c["k"], E, seed=c["seed"], id_bytes=8)
-    rp, col, hist, dups = sfg.edges_to_csr(n, src, dst, flags=0)
+    src, dst, rp, col, hist, dups = sfg.kron_generate_csr(c["n0"], c["initiator"], c["k"], E, seed=c["seed"],
+                                                          id_bytes=8, flags=0)
     torch.cuda.synchronize()
     assert sfg.device_error() == 0
     torch.cuda.empty_cache()
+    _sampled_edges(orc, c, src, dst)
     assert int(rp[0]) == 0 and int(rp[n]) == E
     out = rp[1:] - rp[:-1]
     assert int(out.min()) >= 0

@@ -1,0 +1,117 @@
+"""GPU parity of kron_generate_csr against the oracle: the one-call Kronecker
+graph and its CSR equal the oracle's edge list and the oracle's CSR of it, bit
+for bit, both where the sampler counts the sort's digit histogram (the CSR
+key's digits are whole id bytes and the register-path sampler runs) and where
+the call falls back to the separate histogram pass."""
+import numpy as np
+import pytest
+
+from paper_1003_3684_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+FLAG_SETS = [0, 1, 2, 3]  # directed, symmetrized, simple, symmetrized+simple
+
+
+def _check(sfg, orc, c, flags, want_hist=True, mode=0):
+    import torch
+    n0, W, k, E = c["n0"], c["initiator"], c["k"], c["num_edges"]
+    id_bytes = c.get("id_bytes", 4)
+    print(f"case n0={n0} k={k} E={E} flags={flags} hist={want_hist} mode={mode} ib={id_bytes}", flush=True)
+    src, dst, rp, col, hist, dups = sfg.kron_generate_csr(n0, W, k, E, mode=mode, seed=c.get("seed", 0),
+                                                          graph_id=c.get("graph_id", 0), id_bytes=id_bytes,
+                                                          flags=flags, want_hist=want_hist)
+    torch.cuda.synchronize()
+    assert sfg.device_error() == 0
+    if mode == sfg.KRON_ENUMERATE:
+        os_, od = orc.kron_enumerate((np.asarray(W) != 0).astype(np.uint8), k)
+    else:
+        os_, od = orc.kron_sample(n0, W, k, E, c.get("seed", 0), c.get("graph_id", 0))
+    np.testing.assert_array_equal(src.cpu().numpy().astype(np.int64), os_)
+    np.testing.assert_array_equal(dst.cpu().numpy().astype(np.int64), od)
+    n = n0 ** k
+    orp, ocol, odups = orc.edges_to_csr(n, os_, od, symmetrize=bool(flags & 1), simple=bool(flags & 2))
+    np.testing.assert_array_equal(rp.cpu().numpy().astype(np.uint64), orp)
+    kept = int(orp[-1])
+    np.testing.assert_array_equal(col[:kept].cpu().numpy().astype(np.int64), ocol)
+    assert int(dups.item()) == odups
+    if want_hist:
+        _, ohist = orc.degree_histogram(n, os_, od)
+        np.testing.assert_array_equal(hist.cpu().numpy().astype(np.uint64), ohist)
+
+
+@pytest.mark.parametrize("flags", FLAG_SETS)
+def test_kron_csr_k20(sfg, orc, flags):
+    """2x2 initiator, 20 levels, 2^24 edges (three thresholds, the
+    comparison path): directed keys with whole-byte fields are counted by the
+    sampler; the symmetrized 20-bit fields take the histogram pass."""
+    _check(sfg, orc, wl.KRON_K20, flags)
+
+
+@pytest.mark.parametrize("flags", FLAG_SETS)
+@pytest.mark.parametrize("want_hist", [True, False])
+def test_kron_csr_byte_fields(sfg, orc, flags, want_hist):
+    """Id widths of whole bytes (4^8 = 2^16 and 3^5 = 243 vertices, the
+    latter not a power of two), so every flag set is counted by the sampler,
+    with and without the in-degree field; ragged edge counts."""
+    rng = np.random.default_rng(40 + flags)
+    for n0, k, E in [(4, 8, 300_001), (3, 5, 40_961)]:
+        W = rng.uniform(0.05, 1.0, size=(n0, n0)).astype(np.float32)
+        c = dict(n0=n0, initiator=W, k=k, num_edges=E, seed=int(rng.integers(0, 2 ** 62)),
+                 graph_id=int(rng.integers(0, 1 << 24)), id_bytes=8 if flags & 1 else 4)
+        _check(sfg, orc, c, flags, want_hist)
+
+
+@pytest.mark.parametrize("trial", range(8))
+def test_kron_csr_random(sfg, orc, trial):
+    """Random initiators (up to 15 thresholds: the guide-table path) and
+    sizes, both id widths, every flag set."""
+    rng = np.random.default_rng(7100 + trial)
+    c = wl.random_kron_case(rng)
+    while c["n0"] ** c["k"] > 1 << 26:
+        c = wl.random_kron_case(rng)
+    c["id_bytes"] = 8 if trial % 2 else 4
+    c["graph_id"] = int(rng.integers(0, 1 << 24))
+    _check(sfg, orc, c, FLAG_SETS[trial % 4], want_hist=trial % 3 != 2)
+
+
+def test_kron_csr_fifteen_thresholds(sfg, orc):
+    """A 4x4 initiator with 16 distinct cumulative sums (15 thresholds) at 12
+    levels (24-bit ids: every field whole bytes)."""
+    W = (np.arange(16, dtype=np.float32).reshape(4, 4) + 1.0) / 136.0
+    c = dict(n0=4, initiator=W, k=12, num_edges=1_000_003, seed=99, id_bytes=4)
+    for flags in FLAG_SETS:
+        _check(sfg, orc, c, flags)
+
+
+def test_kron_csr_fallbacks(sfg, orc):
+    """Paths the sampler does not count for: more than 15 thresholds (LDS
+    search) and enumerate mode; results are still those of the oracle."""
+    rng = np.random.default_rng(5)
+    W = rng.uniform(0.0, 1.0, size=(5, 5)).astype(np.float32)
+    _check(sfg, orc, dict(n0=5, initiator=W, k=6, num_edges=70_001, seed=3, id_bytes=8), 0)
+    adj = wl.FIG2_SEED
+    c = dict(n0=5, initiator=adj.astype(np.float32), k=4, num_edges=int(adj.sum()) ** 4)
+    for flags in (0, 3):
+        _check(sfg, orc, c, flags, mode=sfg.KRON_ENUMERATE)
+
+
+def test_kron_csr_edge_cases(sfg, orc):
+    """No edge, one edge, one level, and a single reachable cell."""
+    ones = np.ones((2, 2), np.float32)
+    corner = np.array([[0.0, 0.0], [0.0, 1.0]], np.float32)
+    for c in (dict(n0=2, initiator=ones, k=8, num_edges=0, seed=1),
+              dict(n0=2, initiator=ones, k=8, num_edges=1, seed=1),
+              dict(n0=4, initiator=np.ones((4, 4), np.float32), k=1, num_edges=1000, seed=2),
+              dict(n0=2, initiator=corner, k=16, num_edges=8193, seed=4)):
+        for flags in FLAG_SETS:
+            _check(sfg, orc, c, flags)
+
+
+def test_kron_csr_errors(sfg):
+    import torch
+    with pytest.raises(ValueError):
+        sfg.kron_generate_csr(2, np.ones((2, 2)), 33, 10)
+    with pytest.raises(sfg.SfgenError):
+        sfg.kron_generate_csr(2, np.ones((2, 2)), 4, 10, graph_id=1 << 24)
+    torch.cuda.synchronize()
