@@ -207,13 +207,14 @@ def main():
     fused_hist = hist.clone()
 
     kernels = {}
-    for name in ("kron_sample", "csr_prepare", "radix_pass", "csr_finish", "csr_rowfill", "degree_hist", "fill",
-                 "csr_digit_bases"):
+    for name in ("kron_sample", "csr_prepare", "radix_pass", "csr_run_starts", "csr_finish", "csr_rowfill",
+                 "degree_hist", "fill", "csr_digit_bases"):
         cnt, tot = sfg.profile_query(name)
         if cnt:
             kernels[name] = {"launches_per_step": cnt // args.steps, "ms_per_step": tot / args.steps}
     # Radix pass roofline: pass 0 reads src and dst (16 B) and writes a key
-    # (8 B); every later pass reads and writes one 8-byte key.
+    # (8 B); every later pass reads one 8-byte key and writes one 8-byte key
+    # (the last pass: one 8-byte column).
     passes = kernels["radix_pass"]["launches_per_step"]
     radix_bytes = E * (24 + 16 * (passes - 1))
     radix_ms = kernels["radix_pass"]["ms_per_step"]
