@@ -207,8 +207,8 @@ def main():
     fused_hist = hist.clone()
 
     kernels = {}
-    for name in ("kron_sample", "csr_prepare", "radix_pass", "csr_run_starts", "csr_finish", "csr_rowfill",
-                 "degree_hist", "fill", "csr_digit_bases"):
+    for name in ("kron_sample", "csr_prepare", "radix_pass", "csr_run_starts", "csr_finish", "csr_rowfill", "fill",
+                 "csr_digit_bases"):
         cnt, tot = sfg.profile_query(name)
         if cnt:
             kernels[name] = {"launches_per_step": cnt // args.steps, "ms_per_step": tot / args.steps}

@@ -96,3 +96,27 @@ def test_csr_all_loops_and_empty(sfg, orc):
         _check(sfg, orc, n, src, dst, flags, 4)
     for flags in FLAG_SETS:
         _check(sfg, orc, n, np.zeros(0, np.int64), np.zeros(0, np.int64), flags, 4)
+
+
+@pytest.mark.parametrize("order", ["ascending", "descending", "blocks"])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_csr_sorted_inputs(sfg, orc, order, flags):
+    """Inputs already ordered by source (or in reverse, or in sorted blocks):
+    each digit value of the last pass sits in a few tiles only, so most
+    tiles' runs follow a run of an earlier, non-adjacent tile or of another
+    digit -- the cases the last pass settles after the sort."""
+    rng = np.random.default_rng({"ascending": 1, "descending": 2, "blocks": 3}[order] + 10 * flags)
+    n, E = (1 << 20) + 5, 200_003
+    src = rng.integers(0, n, size=E)
+    dst = rng.integers(0, n, size=E)
+    if order == "ascending":
+        src = np.sort(src)
+    elif order == "descending":
+        src = np.sort(src)[::-1].copy()
+    else:
+        src = np.concatenate([np.sort(b) for b in np.array_split(src, 7)])
+    dst[::97] = src[::97]  # some self-loops
+    dst[1::89] = dst[0:-1:89][: len(dst[1::89])]  # some repeated pairs next to each other
+    src[1::89] = src[0:-1:89][: len(src[1::89])]
+    for ib in (4, 8):
+        _check(sfg, orc, n, src, dst, flags, ib)
