@@ -212,11 +212,11 @@ def main():
         cnt, tot = sfg.profile_query(name)
         if cnt:
             kernels[name] = {"launches_per_step": cnt // args.steps, "ms_per_step": tot / args.steps}
-    # Radix pass roofline: pass 0 reads src and dst (16 B) and writes a key
-    # (8 B); every later pass reads one 8-byte key and writes one 8-byte key
-    # (the last pass: one 8-byte column).
+    # Radix pass roofline: in the one-call path the sampler writes the 8-byte
+    # keys, so every pass reads one key and writes one key (the last pass: one
+    # 8-byte column) -- 16 B per entry and pass.
     passes = kernels["radix_pass"]["launches_per_step"]
-    radix_bytes = E * (24 + 16 * (passes - 1))
+    radix_bytes = E * 16 * passes
     radix_ms = kernels["radix_pass"]["ms_per_step"]
     achieved = radix_bytes / (radix_ms / 1e3) / 1e9
     traffic = _traffic_from_profile(_kernel_source_hash())
@@ -227,7 +227,8 @@ def main():
     # the committed SQ-counter profile (null when the source has changed).
     valu_peak = 256 * 4 * 2.4e9 / 4
     vpe = _valu_per_edge_from_profile()
-    generation = {"edges_per_s": E / (gen_ms / 1e3), "write_GBs": 16 * E / (gen_ms / 1e3) / 1e9, "bound": "alu",
+    # (the sampler writes src, dst and the sort key: 24 B per edge)
+    generation = {"edges_per_s": E / (gen_ms / 1e3), "write_GBs": 24 * E / (gen_ms / 1e3) / 1e9, "bound": "alu",
                   "valu_instr_per_edge": vpe,
                   "alu_frac": None if vpe is None else vpe * E / 64 / (gen_ms / 1e3) / valu_peak,
                   "alu_peak_wave_instr_per_s": valu_peak}

@@ -228,7 +228,9 @@ int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *ds
  * destination field) and the sampler is the register path (sample mode, at
  * most 15 distinct initiator thresholds), the sampler counts the bytes of
  * the ids it writes, and the pass that would read the edge list back to
- * count them is skipped.  Otherwise the call runs the two steps unchanged.
+ * count them is skipped; with 8-byte sort keys it also writes every entry's
+ * key into the workspace, so the first sort pass reads one key per entry
+ * instead of both ids.  Otherwise the call runs the two steps unchanged.
  *
  * Arguments: those of kron_generate and edges_to_csr, with n = n0^k, which
  * must not exceed 2^32.  src and dst are outputs here (device, num_edges ids

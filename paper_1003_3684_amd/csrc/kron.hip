@@ -85,9 +85,13 @@ struct FastArgs {
     uint32_t n0, shift;
     uint32_t tm1[15];
     uint64_t lut_row, lut_col;
-    // Byte counting (ByteCount): LDS rows, flushed into hist at the end.
+    // Byte counting (ByteCount): LDS rows, flushed into hist at the end;
+    // optional sort keys.
     uint64_t *hist;
     int rows, row_mod, dst_row, dst_bytes, src_row, src_bytes;
+    uint64_t *keys;
+    int key_shift;
+    uint64_t key_sym;  // offset of the reversed entries, or 0
 };
 
 constexpr int kCountRows = 8;    // byte-count rows a sampler workgroup keeps in LDS
@@ -184,6 +188,11 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
         src[i] = (IdT)u;
         dst[i] = (IdT)v;
         if (CNT) {
+            if (a.keys) {
+                __builtin_nontemporal_store(((uint64_t)u << a.key_shift) | (uint64_t)v, &a.keys[i]);
+                if (a.key_sym)
+                    __builtin_nontemporal_store(((uint64_t)v << a.key_shift) | (uint64_t)u, &a.keys[a.key_sym + i]);
+            }
 #pragma unroll
             for (int q = 0; q < (int)sizeof(AccT); ++q) {
                 if (q < a.dst_bytes)
@@ -383,6 +392,7 @@ bool count_ok(const ByteCount &bc, uint64_t count, int id_bytes) {
     if (bc.dst_row < 0 || bc.src_row < 0 || bc.dst_row + bc.dst_bytes > kCountRows ||
         bc.src_row + bc.src_bytes > kCountRows)
         return false;
+    if (bc.keys && (bc.key_shift < 1 || bc.key_shift > 32)) return false;
     const uint64_t threads = (uint64_t)grid_for(count) * kBlock;
     const uint64_t per_group = (count + threads - 1) / threads * kBlock;
     return 2 * per_group < (1ull << 32);
@@ -514,6 +524,9 @@ int kron_generate_counted(uint32_t n0, const float *initiator, uint32_t k, uint6
             a.dst_bytes = bc->dst_bytes;
             a.src_row = bc->src_row;
             a.src_bytes = bc->src_bytes;
+            a.keys = bc->keys;
+            a.key_shift = bc->key_shift;
+            a.key_sym = bc->key_sym ? count : 0;
         }
         if (id_bytes == 4)
             launch_fast_any<int32_t, uint32_t>(a, pow2, cnt, tab.nt, src, dst, s);

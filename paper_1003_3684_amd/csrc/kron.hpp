@@ -26,10 +26,17 @@ int build_sample_table(uint32_t n0, const float *W, SampleTable &tab);
 // every source id in row src_row + q (q < src_bytes); at the end
 // hist[r * 256 + value] (uint64) gains the count of row r mod row_mod, for
 // every r < rows (rows <= 8).
+// With keys set, the launch also writes the 8-byte sort key of every edge
+// e: keys[e] = (src << key_shift) | dst, and with key_sym also
+// keys[num_edges + e] = (dst << key_shift) | src (the reversed entry of a
+// symmetrized CSR).
 struct ByteCount {
     uint64_t *hist;
     int rows, row_mod;
     int dst_row, dst_bytes, src_row, src_bytes;
+    uint64_t *keys;
+    int key_shift;
+    bool key_sym;
 };
 
 // kron_generate_range with an optional ByteCount.  *counted tells whether the
