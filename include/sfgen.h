@@ -425,7 +425,8 @@ int ensemble_generate(const sfg_graph_desc *descs, uint32_t count, uint32_t num_
 /* ------------------------------------------------------------------------
  * MLP surrogate -- maps generator parameters to graph statistics; trained on
  * ensembles of generated graphs and inverted to choose parameters for a
- * target degree exponent (the generator stays the judge of the result).
+ * target degree exponent (the generated graph, not the surrogate, decides
+ * whether a result is accepted).
  *
  * Shape: d_in -> width -> ... -> width -> d_out with `hidden` SiLU layers
  * and a linear output layer.  params: device float32, for each layer W

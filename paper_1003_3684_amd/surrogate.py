@@ -1,6 +1,6 @@
 """MLP surrogate: generator parameters -> graph statistics, trained on the
 ensembles the generators produce and inverted to choose Kronecker parameters
-for a target degree exponent.  The real generator stays the judge: a proposal
+for a target degree exponent.  The real generator has the last word: a proposal
 is accepted only when the generated graph's measured exponent is within the
 tolerance, and the generator-only search takes over when the surrogate's
 share of the budget runs out (fit_exponent).
