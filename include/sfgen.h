@@ -236,8 +236,7 @@ int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *ds
  * must not exceed 2^32.  src and dst are outputs here (device, num_edges ids
  * each); the workspace is edges_to_csr_workspace_bytes(n0^k, num_edges,
  * id_bytes, flags) bytes and must not overlap src, dst or the outputs.
- * Errors: those of both calls; when one is returned, src, dst and the CSR
- * outputs are left untouched.
+ * Errors: those of both calls, found before anything is launched.
  * ---------------------------------------------------------------------- */
 int kron_generate_csr(uint32_t n0, const float *initiator, uint32_t k, uint64_t num_edges, int mode, uint64_t seed,
                       uint32_t graph_id, int id_bytes, void *src, void *dst, uint32_t flags, uint64_t *row_ptr,

@@ -121,6 +121,28 @@ def test_csr_validation(lib, host_only):
     assert lib.edges_to_csr(1000, 5000, d, d, 4, 1, d, d, d, None, d, need - 1, None) == -3
 
 
+def test_kron_csr_validation(lib, host_only):
+    """kron_generate_csr checks the generator's and the CSR build's arguments
+    before anything is launched."""
+    _, w = _W([0.5, 0.2, 0.2, 0.1])
+    d = ctypes.c_void_p(256)
+    need = lib.edges_to_csr_workspace_bytes(1 << 10, 5000, 4, 0)
+    assert need > 0
+
+    def call(n0=2, k=10, E=5000, mode=0, graph_id=0, ib=4, flags=0, rp=d, ws=need, W=w):
+        return lib.kron_generate_csr(n0, W, k, E, mode, 1, graph_id, ib, d, d, flags, rp, d, d, d, d, ws, None)
+
+    assert call(n0=1) == -1                 # n0 < 2
+    assert call(k=0) == -1                  # k = 0
+    assert call(k=33) == -2                 # 2^33 vertices: no 64-bit key
+    assert call(flags=8) == -1              # bad flags
+    assert call(ib=3) == -1                 # id bytes
+    assert call(rp=None) == -1              # row_ptr
+    assert call(ws=need - 1) == -3          # workspace
+    assert lib.edges_to_csr_workspace_bytes(1 << 10, 5000, 4, 1) > need  # symmetrized: twice the entries
+    assert call(flags=1, ws=need) == -3
+
+
 def test_workspace_sizes_monotone(lib):
     a = lib.pba_workspace_bytes(1 << 20, 4, 64, 0)
     b = lib.pba_workspace_bytes(1 << 21, 4, 64, 0)
