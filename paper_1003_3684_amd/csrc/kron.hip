@@ -274,7 +274,14 @@ struct EnumArgs {
 // Edge indices below 2^32 (IdxT = uint32_t) take their digits with a
 // multiply-high by `magic`: the estimate is the quotient or one less, and one
 // correction step makes it exact.  AccT holds ids (uint32_t when n0^k <= 2^32).
-template <typename IdT, typename IdxT, typename AccT>
+// A thread writes kEnumRun consecutive edges: they differ only in the lowest
+// digit (the first step's), so after one full decomposition each further edge
+// steps that digit and looks up its pair of table entries; a carry into the
+// next digit (once per `base` edges) decomposes that edge afresh.  VEC: the
+// run is stored with 16-byte vector stores (outputs 16-byte aligned).
+constexpr int kEnumRun = 8;
+
+template <typename IdT, typename IdxT, typename AccT, bool VEC>
 __global__ __launch_bounds__(kBlock) void kron_enumerate_kernel(EnumArgs a, IdT *__restrict__ src,
                                                                 IdT *__restrict__ dst) {
     __shared__ uint16_t s_r[4096], s_c[4096];    // seed edge -> (row, column)
@@ -311,10 +318,13 @@ __global__ __launch_bounds__(kBlock) void kron_enumerate_kernel(EnumArgs a, IdT 
         __syncthreads();
     }
     const uint16_t *tr = pair ? s_r2 : s_r, *tc = pair ? s_c2 : s_c;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < a.num_edges; i += stride) {
-        IdxT rest = (IdxT)(a.e_begin + i);
-        AccT u = 0, v = 0, pw = 1;
+    // Ids of edge e (an index of the whole graph); d0 = its lowest digit.
+    auto decompose = [&](uint64_t e, AccT &u, AccT &v, uint32_t &d0) {
+        IdxT rest = (IdxT)e;
+        AccT pw = 1;
+        u = 0;
+        v = 0;
+        d0 = 0;
         for (uint32_t l = 0; l < a.steps; ++l) {  // least significant digits first
             IdxT q;
             uint32_t d;
@@ -329,6 +339,7 @@ __global__ __launch_bounds__(kBlock) void kron_enumerate_kernel(EnumArgs a, IdT 
                 q = rest / a.base;
                 d = (uint32_t)(rest - q * a.base);
             }
+            if (l == 0) d0 = d;
             rest = q;
             u += (AccT)tr[d] * pw;
             v += (AccT)tc[d] * pw;
@@ -339,8 +350,52 @@ __global__ __launch_bounds__(kBlock) void kron_enumerate_kernel(EnumArgs a, IdT 
             u += (AccT)s_r[d] * pw;
             v += (AccT)s_c[d] * pw;
         }
-        src[i] = (IdT)u;
-        dst[i] = (IdT)v;
+    };
+    // Stepping needs a lowest digit that is a table step (k = 1 has none).
+    const bool step = a.steps > 0;
+    const uint64_t runs = (a.num_edges + kEnumRun - 1) / kEnumRun;
+    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+    for (uint64_t r = (uint64_t)blockIdx.x * kBlock + threadIdx.x; r < runs; r += stride) {
+        const uint64_t i0 = r * kEnumRun;
+        IdT su[kEnumRun], sv[kEnumRun];
+        AccT u, v;
+        uint32_t d0;
+        decompose(a.e_begin + i0, u, v, d0);
+        AccT uh = u - (AccT)tr[d0], vh = v - (AccT)tc[d0];
+        su[0] = (IdT)u;
+        sv[0] = (IdT)v;
+#pragma unroll
+        for (int j = 1; j < kEnumRun; ++j) {
+            if (step && d0 + 1 < a.base) {
+                ++d0;
+                u = uh + (AccT)tr[d0];
+                v = vh + (AccT)tc[d0];
+            } else {
+                decompose(a.e_begin + i0 + j, u, v, d0);
+                uh = u - (AccT)tr[d0];
+                vh = v - (AccT)tc[d0];
+            }
+            su[j] = (IdT)u;
+            sv[j] = (IdT)v;
+        }
+        if (VEC && i0 + kEnumRun <= a.num_edges) {
+            constexpr int kVec = 16 / sizeof(IdT);  // ids per 16-byte store
+#pragma unroll
+            for (int j = 0; j < kEnumRun; j += kVec) {
+                uint4 ws, wd;
+                memcpy(&ws, &su[j], 16);
+                memcpy(&wd, &sv[j], 16);
+                *reinterpret_cast<uint4 *>(src + i0 + j) = ws;
+                *reinterpret_cast<uint4 *>(dst + i0 + j) = wd;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kEnumRun; ++j)
+                if (i0 + j < a.num_edges) {
+                    src[i0 + j] = su[j];
+                    dst[i0 + j] = sv[j];
+                }
+        }
     }
 }
 
@@ -382,6 +437,23 @@ void launch_fast_any(const FastArgs &a, bool pow2, bool cnt, uint32_t nt, void *
         launch_fast<IdT, AccT, false, true>(a, nt, src, dst, s);
     else
         launch_fast<IdT, AccT, false, false>(a, nt, src, dst, s);
+}
+
+template <bool VEC>
+void launch_enumerate(const EnumArgs &a, int id_bytes, bool idx32, bool acc32, int g, void *src, void *dst,
+                      hipStream_t s) {
+    if (id_bytes == 4 && idx32)  // int32 ids: n0^k <= 2^31
+        kron_enumerate_kernel<int32_t, uint32_t, uint32_t, VEC><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst);
+    else if (id_bytes == 4)
+        kron_enumerate_kernel<int32_t, uint64_t, uint32_t, VEC><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst);
+    else if (idx32 && acc32)
+        kron_enumerate_kernel<int64_t, uint32_t, uint32_t, VEC><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
+    else if (idx32)
+        kron_enumerate_kernel<int64_t, uint32_t, uint64_t, VEC><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
+    else if (acc32)
+        kron_enumerate_kernel<int64_t, uint64_t, uint32_t, VEC><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
+    else
+        kron_enumerate_kernel<int64_t, uint64_t, uint64_t, VEC><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
 }
 
 // Whether a ByteCount request is one the register path can take: rows inside
@@ -473,21 +545,14 @@ int kron_generate_counted(uint32_t n0, const float *initiator, uint32_t k, uint6
         a.odd = pair ? (k & 1) : 0;
         a.magic = 0xFFFFFFFFu / a.base;
         a.place = pair ? n0 * n0 : n0;
-        const int g = grid_for(count);
+        const int g = grid_for((count + kEnumRun - 1) / kEnumRun);
         const bool idx32 = ne <= (1ull << 32);
+        const bool vec = ((uintptr_t)src % 16 == 0) && ((uintptr_t)dst % 16 == 0);
         ProfScope _ps("kron_enumerate", s);
-        if (id_bytes == 4 && idx32)  // int32 ids: n0^k <= 2^31
-            kron_enumerate_kernel<int32_t, uint32_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst);
-        else if (id_bytes == 4)
-            kron_enumerate_kernel<int32_t, uint64_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int32_t *)src, (int32_t *)dst);
-        else if (idx32 && acc32)
-            kron_enumerate_kernel<int64_t, uint32_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
-        else if (idx32)
-            kron_enumerate_kernel<int64_t, uint32_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
-        else if (acc32)
-            kron_enumerate_kernel<int64_t, uint64_t, uint32_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
+        if (vec)
+            launch_enumerate<true>(a, id_bytes, idx32, acc32, g, src, dst, s);
         else
-            kron_enumerate_kernel<int64_t, uint64_t, uint64_t><<<g, kBlock, 0, s>>>(a, (int64_t *)src, (int64_t *)dst);
+            launch_enumerate<false>(a, id_bytes, idx32, acc32, g, src, dst, s);
         return check_launch("kron_generate(enumerate)");
     }
 

@@ -141,3 +141,30 @@ def test_kron_scale_sampled(sfg, orc):
 def test_kron_scale_unpadded_sampled(sfg, orc):
     """The same edge count with the unpadded 3x3 initiator and 19 levels."""
     _sampled_check(sfg, orc, wl.KRON_SCALE_B)
+
+
+@pytest.mark.parametrize("id_bytes", [4, 8])
+def test_kron_enumerate_unaligned_and_ranges(sfg, orc, id_bytes):
+    """Enumerate mode into outputs that are not 16-byte aligned (the scalar
+    store path) and over edge ranges that start and end inside a thread's run
+    of consecutive edges."""
+    import torch
+    adj = wl.FIG2_SEED
+    k = 5
+    E = int(adj.sum()) ** k
+    os_, od = orc.kron_enumerate(adj, k)
+    dt = torch.int32 if id_bytes == 4 else torch.int64
+    bs = torch.empty(E + 3, dtype=dt, device="cuda")
+    bd = torch.empty(E + 3, dtype=dt, device="cuda")
+    src, dst = sfg.kron_generate(5, adj.astype(np.float32), k, E, mode=sfg.KRON_ENUMERATE, id_bytes=id_bytes,
+                                 src=bs[1:E + 1], dst=bd[3:E + 3])
+    torch.cuda.synchronize()
+    assert sfg.device_error() == 0
+    np.testing.assert_array_equal(src.cpu().numpy().astype(np.int64), os_)
+    np.testing.assert_array_equal(dst.cpu().numpy().astype(np.int64), od)
+    for b, c in [(1, 1000), (12345, 777), (E - 13, 13), (120, 2)]:
+        s, d = sfg.kron_generate_range(5, adj.astype(np.float32), k, E, b, c, mode=sfg.KRON_ENUMERATE,
+                                       id_bytes=id_bytes)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(s.cpu().numpy().astype(np.int64), os_[b:b + c])
+        np.testing.assert_array_equal(d.cpu().numpy().astype(np.int64), od[b:b + c])
