@@ -16,8 +16,8 @@ on a bounded sample of the same workload, the PBA workload (2^27 vertices,
 m = 5, 1,024 partitions), PBA generation at the paper's largest size (2^30
 vertices, m = 5), the batched-versus-plain ensemble rate (4,096 PBA and
 Kronecker graphs with their statistics, batch budget from the autotuner),
-the enumerated Kronecker power of the Fig. 2 seed and one surrogate training
-step.
+the enumerated Kronecker power of the Fig. 2 seed, the two randomized PK
+variants and the block matrix on that seed, and one surrogate training step.
 """
 import argparse
 import hashlib
@@ -274,7 +274,8 @@ def main():
     if not args.no_extras:
         result["extras"] = {"pba": _bench_pba(sfg, wl, torch), "pba_paper_scale": _bench_pba_paper(sfg, wl, torch),
                             "ensemble": _bench_ensemble(sfg, wl, torch),
-                            "kron_enumerate": _bench_enumerate(sfg, wl, torch), "mlp": _bench_mlp(sfg, torch)}
+                            "kron_enumerate": _bench_enumerate(sfg, wl, torch),
+                            "randomized_pk": _bench_randomized_pk(sfg, wl, torch), "mlp": _bench_mlp(sfg, torch)}
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_sample)
     print(json.dumps(result), flush=True)
@@ -357,6 +358,47 @@ def _bench_pba(sfg, wl, torch, reps=3):
     del src, dst, rp, col, pws
     torch.cuda.empty_cache()
     return out
+
+
+def _timed(torch, fn, reps=3):
+    """Milliseconds per call of fn on the current stream (after one warm-up)."""
+    out = fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        out = fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps, out
+
+
+def _bench_randomized_pk(sfg, wl, torch, k=8):
+    """The paper's two randomizations of the PK power and the community
+    report, on the Fig. 2 seed at 8 levels (11^8 = 2.1e8 edges, 5^8
+    vertices, int32 ids): the seed modified per meta-edge expansion
+    (p_add = p_del = 0.05), the power XOR a random graph of 10^8 uniform
+    pair draws (sorted into one CSR), and the 25 x 25 block matrix of the
+    modified graph."""
+    W = wl.FIG2_SEED.astype("float32")
+    n = 5 ** k
+    cap = 3 * 10 ** 8
+    ws = sfg.workspace(sfg.load().kron_perturbed_workspace_bytes(cap))
+    ms1, (src, dst) = _timed(torch, lambda: sfg.kron_perturbed(5, W, k, 0.05, 0.05, cap, seed=5, ws=ws))
+    m = src.numel()
+    ms3, _ = _timed(torch, lambda: sfg.block_matrix(n, src, dst, 25))
+    del src, dst, ws
+    torch.cuda.empty_cache()
+    R = 10 ** 8
+    ms2, (rp, col) = _timed(torch, lambda: sfg.kron_xor_random(5, W, k, R, seed=5))
+    kept = int(rp[n])
+    del rp, col
+    torch.cuda.empty_cache()
+    return {"workload": f"fig2_seed_k{k}",
+            "modified_seed": {"edges": m, "ms": ms1, "edges_per_s": m / (ms1 / 1e3)},
+            "xor_random": {"power_edges": 11 ** k, "random_pairs": R, "kept": kept, "ms": ms2,
+                           "entries_per_s": (11 ** k + R) / (ms2 / 1e3)},
+            "block_matrix": {"edges": m, "blocks": 25, "ms": ms3, "edges_per_s": m / (ms3 / 1e3)}}
 
 
 def _bench_enumerate(sfg, wl, torch, k=9, reps=5):
