@@ -121,22 +121,51 @@ __global__ __launch_bounds__(kPtThreads) void pt_scan_apply(const uint32_t *fan,
         }
 }
 
-// Children of every meta-edge, in cell order, at its scanned offset.
+// Children of every meta-edge, in cell order, at its scanned offset.  A
+// workgroup takes kPtThreads consecutive meta-edges, whose children form one
+// contiguous output range [off[first], end); when that range fits kExpStage
+// entries the children are gathered in LDS and the range is written
+// coalesced, else every thread writes its own children.  total: the number of
+// children of the whole level (the end of the last range).
+constexpr int kExpStage = 4096;
+
 template <typename OutT>
 __global__ __launch_bounds__(kPtThreads) void pt_expand(PtArgs a, uint32_t it, uint64_t count, const uint32_t *row,
-                                                        const uint32_t *col, const uint64_t *off, OutT *nrow,
-                                                        OutT *ncol) {
+                                                        const uint32_t *col, const uint64_t *off, uint64_t total,
+                                                        OutT *nrow, OutT *ncol) {
+    __shared__ OutT s_r[kExpStage], s_c[kExpStage];
     const uint64_t stride = (uint64_t)gridDim.x * kPtThreads;
-    for (uint64_t j = (uint64_t)blockIdx.x * kPtThreads + threadIdx.x; j < count; j += stride) {
-        const uint32_t r = row[j], c = col[j];
-        uint64_t m = perturbed_mask(a, it, r, c);
-        uint64_t o = off[j];
-        while (m) {
-            const uint32_t cell = (uint32_t)__builtin_ctzll(m);
-            m &= m - 1;
-            nrow[o] = (OutT)((uint64_t)r * a.n0 + cell / a.n0);
-            ncol[o] = (OutT)((uint64_t)c * a.n0 + cell % a.n0);
-            ++o;
+    for (uint64_t base = (uint64_t)blockIdx.x * kPtThreads; base < count; base += stride) {
+        const uint64_t j = base + threadIdx.x;
+        const uint64_t last = min(base + kPtThreads, count);  // one past the block's meta-edges
+        const uint64_t o0 = off[base], o_end = last < count ? off[last] : total;
+        const bool stage = o_end - o0 <= (uint64_t)kExpStage;
+        if (j < count) {
+            const uint32_t r = row[j], c = col[j];
+            uint64_t m = perturbed_mask(a, it, r, c);
+            uint64_t o = off[j];
+            while (m) {
+                const uint32_t cell = (uint32_t)__builtin_ctzll(m);
+                m &= m - 1;
+                const OutT vr = (OutT)((uint64_t)r * a.n0 + cell / a.n0);
+                const OutT vc = (OutT)((uint64_t)c * a.n0 + cell % a.n0);
+                if (stage) {
+                    s_r[o - o0] = vr;
+                    s_c[o - o0] = vc;
+                } else {
+                    nrow[o] = vr;
+                    ncol[o] = vc;
+                }
+                ++o;
+            }
+        }
+        if (stage) {
+            __syncthreads();
+            for (uint64_t i = threadIdx.x; i < o_end - o0; i += kPtThreads) {
+                nrow[o0 + i] = s_r[i];
+                ncol[o0 + i] = s_c[i];
+            }
+            __syncthreads();
         }
     }
 }
@@ -260,13 +289,13 @@ extern "C" int kron_perturbed(uint32_t n0, const float *seed_matrix, uint32_t k,
         ProfScope _ps("perturb_expand", s);
         if (it + 1 == k) {
             if (id_bytes == 4)
-                pt_expand<int32_t><<<g, kPtThreads, 0, s>>>(a, it, count, r0, c0, off, static_cast<int32_t *>(src),
-                                                            static_cast<int32_t *>(dst));
+                pt_expand<int32_t><<<g, kPtThreads, 0, s>>>(a, it, count, r0, c0, off, next,
+                                                            static_cast<int32_t *>(src), static_cast<int32_t *>(dst));
             else
-                pt_expand<int64_t><<<g, kPtThreads, 0, s>>>(a, it, count, r0, c0, off, static_cast<int64_t *>(src),
-                                                            static_cast<int64_t *>(dst));
+                pt_expand<int64_t><<<g, kPtThreads, 0, s>>>(a, it, count, r0, c0, off, next,
+                                                            static_cast<int64_t *>(src), static_cast<int64_t *>(dst));
         } else {
-            pt_expand<uint32_t><<<g, kPtThreads, 0, s>>>(a, it, count, r0, c0, off, r1, c1);
+            pt_expand<uint32_t><<<g, kPtThreads, 0, s>>>(a, it, count, r0, c0, off, next, r1, c1);
             std::swap(r0, r1);
             std::swap(c0, c1);
         }
