@@ -21,8 +21,14 @@ template <typename IdT, bool LDS>
 __global__ __launch_bounds__(kCommThreads) void block_count(uint64_t n, uint64_t E, const IdT *src, const IdT *dst,
                                                            uint32_t B, unsigned long long *counts) {
     __shared__ uint32_t s_c[LDS ? kLdsBlocks * kLdsBlocks : 1];
+    // Small matrices keep 2 or 4 interleaved copies of every cell (lane l
+    // counts in copy l mod copies): the edges of a skewed graph crowd into a
+    // few cells, whose LDS atomics would otherwise serialise.
+    const uint32_t cells = B * B;
+    const uint32_t copies = !LDS ? 1u : cells * 4 <= kLdsBlocks * kLdsBlocks ? 4u : cells * 2 <= kLdsBlocks * kLdsBlocks ? 2u : 1u;
+    const uint32_t copy = threadIdx.x % copies;
     if (LDS) {
-        for (uint32_t i = threadIdx.x; i < B * B; i += kCommThreads) s_c[i] = 0;
+        for (uint32_t i = threadIdx.x; i < cells * copies; i += kCommThreads) s_c[i] = 0;
         __syncthreads();
     }
     // floor(u B / n) by multiply-high (magic = floor((2^64 - 1) / n); the
@@ -40,14 +46,17 @@ __global__ __launch_bounds__(kCommThreads) void block_count(uint64_t n, uint64_t
         if (u >= n || v >= n) continue;  // not a vertex: not counted
         const uint32_t bi = block_of(u), bj = block_of(v);
         if (LDS)
-            atomicAdd(&s_c[bi * B + bj], 1u);
+            atomicAdd(&s_c[(bi * B + bj) * copies + copy], 1u);
         else
             atomicAdd(&counts[(uint64_t)bi * B + bj], 1ull);
     }
     if (LDS) {
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < B * B; i += kCommThreads)
-            if (s_c[i]) atomicAdd(&counts[i], (unsigned long long)s_c[i]);
+        for (uint32_t i = threadIdx.x; i < cells; i += kCommThreads) {
+            uint32_t t = 0;
+            for (uint32_t c = 0; c < copies; ++c) t += s_c[i * copies + c];
+            if (t) atomicAdd(&counts[i], (unsigned long long)t);
+        }
     }
 }
 
