@@ -56,6 +56,7 @@ def _load():
         "orc_gamma_mle": (C.c_double, [C.c_uint64, u64p, C.c_uint64]),
         "orc_simple_csr": (C.c_int64, [C.c_uint64, C.c_uint64, i64p, i64p, u64p, i64p]),
         "orc_wedge_closed": (C.c_int64, [C.c_uint64, u64p, i64p, C.c_uint32, C.c_uint64, C.c_uint32]),
+        "orc_wedge_draws": (C.c_int64, [C.c_uint64, u64p, i64p, C.c_uint32, C.c_uint64, C.c_uint32, i64p]),
         "orc_path_stats": (None, [C.c_uint64, u64p, i64p, i64p, C.c_uint32, u64p, u64p, u64p]),
         "orc_kron_xor_random": (C.c_int64, [C.c_uint32, u8p, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint32,
                                             u64p, i64p]),
@@ -232,6 +233,18 @@ def wedge_closed(n, row_ptr, col, num_samples, seed, graph_id=0):
     if col.size == 0:
         col = np.zeros(1, np.int64)
     return int(_load().orc_wedge_closed(n, row_ptr, col, num_samples, seed, graph_id))
+
+
+def wedge_draws(n, row_ptr, col, num_samples, seed, graph_id=0):
+    """(closed count, [num_samples, 3] array of (centre, a, b)) of the wedge
+    samples; (-1, None) when the graph has no wedge."""
+    row_ptr = np.ascontiguousarray(row_ptr, np.uint64)
+    col = np.ascontiguousarray(col, np.int64)
+    if col.size == 0:
+        col = np.zeros(1, np.int64)
+    out = np.zeros((max(num_samples, 1), 3), np.int64)
+    closed = int(_load().orc_wedge_draws(n, row_ptr, col, num_samples, seed, graph_id, out))
+    return (closed, out[:num_samples]) if closed >= 0 else (-1, None)
 
 
 def path_stats(n, row_ptr, col, sources):

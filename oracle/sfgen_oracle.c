@@ -511,12 +511,19 @@ static int has_neighbor(const uint64_t *row_ptr, const int64_t *col, int64_t v, 
     return lo < row_ptr[v + 1] && col[lo] == w;
 }
 
-/* Wedge sampling on a simple undirected CSR: sample i picks the centre v with
- * probability proportional to C(d_v, 2), then two distinct neighbours a != b
- * uniformly; the wedge is closed when a and b are adjacent.  Returns the
- * number of closed wedges among num_samples, or -1 if the graph has no wedge. */
-int64_t orc_wedge_closed(uint64_t n, const uint64_t *row_ptr, const int64_t *col, uint32_t num_samples,
-                         uint64_t seed, uint32_t gid)
+/* Wedge sampling on a simple undirected CSR (Results: the clustering the
+ * paper compares is estimated here by sampled wedges).  Sample i picks the
+ * centre v with probability proportional to C(d_v, 2) -- the first vertex
+ * whose inclusive prefix of C(d, 2) exceeds a uniform index in [0, total) --
+ * then two distinct neighbours a != b uniformly; the wedge is closed when a
+ * and b are adjacent.
+ *
+ * orc_wedge_draws writes (v, a, b) of samples 0 .. num_samples-1 into out[3 i
+ * .. 3 i + 2] (a and b are the neighbours' ids) and returns the number of
+ * closed ones; orc_wedge_closed returns only that number.  Both return -1 if
+ * the graph has no wedge (out is then untouched). */
+int64_t orc_wedge_draws(uint64_t n, const uint64_t *row_ptr, const int64_t *col, uint32_t num_samples,
+                        uint64_t seed, uint32_t gid, int64_t *out)
 {
     uint64_t *pre = (uint64_t *)malloc(sizeof(uint64_t) * (n ? n : 1));
     if (!pre) return -1;
@@ -546,9 +553,20 @@ int64_t orc_wedge_closed(uint64_t n, const uint64_t *row_ptr, const int64_t *col
         if (b >= a) b += 1;
         int64_t na = col[row_ptr[v] + a], nb = col[row_ptr[v] + b];
         closed += has_neighbor(row_ptr, col, na, nb);
+        if (out) {
+            out[3 * (uint64_t)i] = (int64_t)v;
+            out[3 * (uint64_t)i + 1] = na;
+            out[3 * (uint64_t)i + 2] = nb;
+        }
     }
     free(pre);
     return closed;
+}
+
+int64_t orc_wedge_closed(uint64_t n, const uint64_t *row_ptr, const int64_t *col, uint32_t num_samples,
+                         uint64_t seed, uint32_t gid)
+{
+    return orc_wedge_draws(n, row_ptr, col, num_samples, seed, gid, NULL);
 }
 
 /* ------------------------------------------------------------------------

@@ -457,6 +457,93 @@ def _transitivity(n, rp, col):
     return 3 * tri / wedges
 
 
+def _simple_undirected_numpy(n, src, dst):
+    """Row starts and columns of the simple undirected graph: both
+    orientations of every non-loop edge, repeats removed (numpy.unique)."""
+    u = np.concatenate([src, dst]).astype(np.int64)
+    v = np.concatenate([dst, src]).astype(np.int64)
+    keep = u != v
+    key = np.unique(u[keep] * n + v[keep])
+    rows, cols = key // n, key % n
+    return np.concatenate([[0], np.cumsum(np.bincount(rows, minlength=n))]).astype(np.uint64), cols
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_simple_csr_matches_numpy_unique(orc, seed):
+    """The simple undirected graph the wedge statistics run on: self-loops
+    dropped, both orientations, every pair once.  Inputs carry many
+    self-loops and repeated pairs in both orientations."""
+    rng = np.random.default_rng(300 + seed)
+    n, E = 64, 3000
+    src = rng.integers(0, n, size=E)
+    dst = np.where(rng.uniform(size=E) < 0.2, src, rng.integers(0, n, size=E))  # ~20 % self-loops
+    dup = rng.integers(0, E, size=E // 4)
+    src = np.concatenate([src, dst[dup], src[dup]])  # repeats, reversed and straight
+    dst = np.concatenate([dst, src[dup], dst[dup]])
+    assert np.any(src == dst)
+    rp, col = orc.simple_csr(n, src, dst)
+    erp, ecol = _simple_undirected_numpy(n, src, dst)
+    np.testing.assert_array_equal(rp, erp)
+    np.testing.assert_array_equal(col, ecol)
+    assert not np.any(np.repeat(np.arange(n), np.diff(rp.astype(np.int64))) == col)  # no loop survives
+    # the same graph through the general CSR with SYMMETRIZE | SIMPLE
+    rp2, col2, _ = orc.edges_to_csr(n, src, dst, symmetrize=True, simple=True)
+    np.testing.assert_array_equal(rp2, erp)
+    np.testing.assert_array_equal(col2, ecol)
+
+
+def _wedge_boundary_graph():
+    """A small simple graph whose vertex order puts vertices without wedges
+    (degree 0 or 1) first and right after each boundary of the cumulative
+    C(d, 2) list, so that sampled indices equal to a prefix value are common."""
+    edges = [(0, 1), (1, 4), (4, 5), (4, 6), (5, 6), (6, 8), (3, 8), (8, 9), (9, 10), (10, 11), (12, 13),
+             (13, 14), (14, 12), (14, 15)]
+    n = 17  # vertices 2, 7 and 16 are isolated
+    a = np.array(edges, np.int64)
+    return n, a[:, 0], a[:, 1]
+
+
+@pytest.mark.parametrize("case", ["boundary", "random_sparse"])
+def test_wedge_centres_brute_force(orc, case):
+    """Every sampled centre is the vertex the definition picks: the first
+    vertex whose inclusive running sum of C(d, 2) exceeds the sampled index
+    floor(U acc / 2^64), found here by a plain linear scan.  Every centre has
+    degree >= 2, its two ends are distinct neighbours, and 'closed' is the
+    adjacency of the two ends (a set lookup)."""
+    if case == "boundary":
+        n, src, dst = _wedge_boundary_graph()
+    else:
+        rng = np.random.default_rng(77)
+        n = 400
+        src = rng.integers(0, n, size=300)
+        dst = rng.integers(0, n, size=300)
+    rp, col = orc.simple_csr(n, src, dst)
+    rp = rp.astype(np.int64)
+    nbrs = [set(col[rp[v]:rp[v + 1]].tolist()) for v in range(n)]
+    deg = [len(s) for s in nbrs]
+    cum, acc = [], 0
+    for d in deg:
+        acc += d * (d - 1) // 2
+        cum.append(acc)
+    N, seed, gid = 4000, 29, 3
+    closed, draws = orc.wedge_draws(n, rp.astype(np.uint64), col, N, seed, gid)
+    expect_closed = 0
+    for i in range(N):
+        w = orc.philox([i, 0, 0, 4 | (gid << 8)], [seed & 0xFFFFFFFF, seed >> 32])
+        U = int(w[0]) | (int(w[1]) << 32)
+        target = (U * acc) >> 64
+        v = 0
+        while cum[v] <= target:
+            v += 1
+        c, a, b = (int(x) for x in draws[i])
+        assert c == v, (i, target, c, v)
+        assert deg[c] >= 2
+        assert a != b and a in nbrs[c] and b in nbrs[c]
+        expect_closed += b in nbrs[a]
+    assert closed == expect_closed
+    assert closed == orc.wedge_closed(n, rp.astype(np.uint64), col, N, seed, gid)
+
+
 def test_wedges_special_graphs(orc):
     # complete graph: every wedge closed; star and cycle: none
     n = 12
