@@ -126,6 +126,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=1 << 25, help="edges in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the PBA and ensemble extras")
+    ap.add_argument("--only", choices=("pba",), default=None,
+                    help="run only one part and print its JSON: 'pba' = PBA generation at 2^27 and 2^30 vertices "
+                         "with per-kernel times (for profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy three times (the reference kernel of known "
                          "size for scaling the HBM byte counters) and exit")
@@ -139,6 +142,14 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read_per_copy": a.numel() * 8,
                           "bytes_written_per_copy": a.numel() * 8, "copies": 3}), flush=True)
+        return
+    if args.only == "pba":
+        import torch
+        from paper_1003_3684_amd import native as sfg
+        from paper_1003_3684_amd import workloads as wl
+        sfg.load()
+        print(json.dumps({"pba": _bench_pba(sfg, wl, torch, paths=False),
+                          "pba_paper_scale": _bench_pba_paper(sfg, wl, torch)}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU sharding is a design note, "
@@ -281,6 +292,25 @@ def main():
     print(json.dumps(result), flush=True)
 
 
+PBA_KERNELS = ("pba_draw1", "pba_resolve", "pba_tile_table", "pba_count", "pba_scan", "pba_draw2",
+               "pba_substitute", "fill")
+
+
+def _pba_breakdown(sfg, gen, reps):
+    """Per-kernel milliseconds per generation, from the library's launch events."""
+    sfg.profile_reset()
+    sfg.profile_enable(True)
+    for _ in range(reps):
+        gen()
+    sfg.profile_enable(False)
+    out = {}
+    for name in PBA_KERNELS:
+        cnt, tot = sfg.profile_query(name)
+        if cnt:
+            out[name] = {"launches": cnt // reps, "ms": tot / reps}
+    return out
+
+
 def _bench_pba_paper(sfg, wl, torch, reps=2):
     """PBA generation at the paper's largest size: 2^30 vertices, m = 5
     (5.4e9 edges, int32), 1,024 partitions, p = 0.1; edge list only, as the
@@ -304,13 +334,15 @@ def _bench_pba_paper(sfg, wl, torch, reps=2):
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
+    kernels = _pba_breakdown(sfg, gen, reps)
     del src, dst, ws
     torch.cuda.empty_cache()
     return {"workload": c["name"], "edges": E, "gen_ms": ms, "gen_edges_per_s": E / (ms / 1e3),
+            "kernels": kernels,
             "paper_context": "under 13 s for 1e9 vertices and 5e9 edges on 1,024 processors of a cluster"}
 
 
-def _bench_pba(sfg, wl, torch, reps=3):
+def _bench_pba(sfg, wl, torch, reps=3, paths=True):
     """PBA at 2^27 vertices, m = 5, 1,024 partitions, p = 0.1: generation plus
     the symmetrized CSR with degree histogram."""
     c = wl.PBA_SCALE[1]
@@ -342,7 +374,12 @@ def _bench_pba(sfg, wl, torch, reps=3):
     torch.cuda.synchronize()
     gen_ms, csr_ms = a.elapsed_time(b) / reps, b.elapsed_time(d) / reps
     out = {"workload": c["name"], "edges": E, "gen_ms": gen_ms, "gen_edges_per_s": E / (gen_ms / 1e3),
-           "csr_ms": csr_ms, "step_edges_per_s": E / ((gen_ms + csr_ms) / 1e3)}
+           "csr_ms": csr_ms, "step_edges_per_s": E / ((gen_ms + csr_ms) / 1e3),
+           "kernels": _pba_breakdown(sfg, gen, reps)}
+    if not paths:
+        del src, dst, rp, col, ws
+        torch.cuda.empty_cache()
+        return out
     # Table 2 analogue: average path length and diameter estimate from 64
     # sampled sources, on the symmetrized graph.
     import numpy as np

@@ -75,6 +75,60 @@ def test_ensemble_members_match_oracle(sfg, orc):
             assert abs(gamma[i] - og) <= 1e-9 * abs(og)
 
 
+def _oracle_member_stats(orc, r, samples, stat_seed):
+    if r["kind"] == "pba":
+        src, dst = orc.pba_generate(r["n"], r["m"], r["num_parts"], r["p_inter"], r["seed"], r["graph_id"])
+        n = r["n"]
+    else:
+        src, dst = orc.kron_sample(r["n0"], r["initiator"], r["k"], r["num_edges"], r["seed"], r["graph_id"])
+        n = r["n0"] ** r["k"]
+    return orc.graph_stats(n, src, dst, samples, stat_seed, r["graph_id"])
+
+
+@pytest.mark.timeout(600)
+def test_full_ensemble_table_members_match_oracle(sfg, orc):
+    """The 4,096-graph ensemble table of the benchmark (PBA n up to 2^20,
+    Kronecker k up to 20 with 16 * 2^k edges) through ensemble_generate:
+    the largest PBA member, a Kronecker member at k = 20, and 16 more members
+    drawn across the table equal the oracle's statistics (histogram and
+    closed-wedge count exactly, the exponent within 1e-9 relative: the two
+    sum the logarithms in different orders)."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    rows = wl.ensemble_table()
+    samples, stat_seed = 10_000, 5
+    descs = sfg.graph_descs(rows)
+    hist, gamma, closed = sfg.ensemble_generate(descs, num_samples=samples, stat_seed=stat_seed,
+                                                max_batch_edges=1 << 27)
+    torch.cuda.synchronize()
+    assert sfg.device_error() == 0
+    hist, gamma, closed = hist.cpu().numpy(), gamma.cpu().numpy(), closed.cpu().numpy()
+
+    def size(r):
+        return r["n"] * r["m"] if r["kind"] == "pba" else r["num_edges"]
+
+    pba = [i for i, r in enumerate(rows) if r["kind"] == "pba"]
+    kron = [i for i, r in enumerate(rows) if r["kind"] == "kron"]
+    pick = {max(pba, key=lambda i: rows[i]["n"]), next(i for i in kron if rows[i]["k"] == 20)}
+    rng = np.random.default_rng(2024)
+    pick |= set(int(i) for i in rng.choice(len(rows), size=16, replace=False))
+    pick = sorted(pick)
+    assert len(pick) >= 17 and max(rows[i]["n"] for i in pick if rows[i]["kind"] == "pba") > 1 << 19
+    threads = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else 4))
+    with ThreadPoolExecutor(threads) as ex:
+        want = list(ex.map(lambda i: _oracle_member_stats(orc, rows[i], samples, stat_seed),
+                           sorted(pick, key=lambda i: -size(rows[i]))))
+    for i, (oh, og, oc) in zip(sorted(pick, key=lambda i: -size(rows[i])), want):
+        np.testing.assert_array_equal(hist[i].astype(np.uint64), oh, err_msg=f"member {i}")
+        assert closed[i] == oc, (i, closed[i], oc)
+        if math.isnan(og):
+            assert math.isnan(gamma[i]), i
+        else:
+            assert abs(gamma[i] - og) <= 1e-9 * abs(og), (i, gamma[i], og)
+
+
 def test_ensemble_workspace_and_errors(sfg):
     """Several batches: the reported size holds two halves, and the batches
     alternate between two streams; half of it runs them one after another on

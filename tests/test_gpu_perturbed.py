@@ -10,6 +10,7 @@ pytestmark = pytest.mark.gpu
 
 FIG2 = wl.FIG2_SEED.astype(np.float32)
 SEED3 = np.array([[1, 1, 0], [0, 1, 1], [1, 0, 0]], np.float32)
+ONES8 = np.ones((8, 8), np.float32)
 
 
 @pytest.mark.parametrize("seed_m,k,p_add,p_del,id_bytes", [
@@ -19,6 +20,10 @@ SEED3 = np.array([[1, 1, 0], [0, 1, 1], [1, 0, 0]], np.float32)
     (SEED3, 9, 0.2, 0.3, 8),      # 64-bit ids
     (SEED3, 5, 1.0, 1.0, 4),      # every cell flipped: seed (x) complement^4
     (SEED3, 4, 0.0, 1.0, 4),      # everything deleted below the first level
+    # ~58 children per meta-edge: a workgroup's children overflow its LDS
+    # staging area and are written directly
+    (ONES8, 3, 0.0, 0.1, 4),
+    (ONES8, 3, 0.0, 0.1, 8),
 ])
 def test_matches_oracle(sfg, orc, seed_m, k, p_add, p_del, id_bytes):
     import torch
