@@ -21,7 +21,8 @@
  *     HIP device; "host" pointers are read before the call returns and not
  *     retained.  The caller owns every buffer.  No entry point allocates
  *     device memory: scratch space is the caller's workspace, sized by the
- *     matching *_workspace_bytes function.
+ *     matching *_workspace_bytes function (edges_to_csr_noalloc uses a static
+ *     array of the library instead).
  *   - `stream` is a hipStream_t (NULL = the default stream).  Work is
  *     enqueued asynchronously on it; faults inside kernels surface at the
  *     next synchronisation of that stream.
@@ -211,6 +212,29 @@ size_t edges_to_csr_workspace_bytes(uint64_t n, uint64_t num_edges, int id_bytes
 int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes, uint32_t flags,
                  uint64_t *row_ptr, void *col, uint64_t *degree_hist32, uint64_t *num_duplicates,
                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * edges_to_csr_noalloc -- edges_to_csr for callers that cannot allocate
+ * device memory or pass a workspace: code under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc.
+ *
+ * Same arguments, outputs and errors as edges_to_csr, without the workspace:
+ * the scratch space is a static device array of the library,
+ * edges_to_csr_noalloc_max_bytes() bytes (64 MiB) per device, held from the
+ * first use on that device until the process ends.  The call allocates
+ * nothing (with launch timing off: sfg_profile_enable creates its timing
+ * events on demand).  A problem whose edges_to_csr_workspace_bytes exceeds
+ * the array fails with ERANGE before anything is enqueued (e.g. 1.5 M edges
+ * over 2^20 vertices fit with every flag).  Every call on one device shares
+ * that device's array and finds the last call's contents there (the call
+ * clears what it needs): calls that overlap in time on one device -- on two
+ * streams, or from two host threads without ordering -- race and must not be
+ * made.
+ * ---------------------------------------------------------------------- */
+size_t edges_to_csr_noalloc_max_bytes(void);
+int edges_to_csr_noalloc(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes,
+                         uint32_t flags, uint64_t *row_ptr, void *col, uint64_t *degree_hist32,
+                         uint64_t *num_duplicates, void *stream);
 
 /* ------------------------------------------------------------------------
  * kron_generate_csr -- a Kronecker graph and its CSR in one call (the PK

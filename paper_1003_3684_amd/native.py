@@ -44,6 +44,8 @@ SIGNATURES = {
     "pba_generate": (_i32, [_u64, _u32, _u32, _dbl, _vp, _vp, _u64, _u32, _i32, _vp, _vp, _vp, _sz, _vp]),
     "edges_to_csr_workspace_bytes": (_sz, [_u64, _u64, _i32, _u32]),
     "edges_to_csr": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "edges_to_csr_noalloc_max_bytes": (_sz, []),
+    "edges_to_csr_noalloc": (_i32, [_u64, _u64, _vp, _vp, _i32, _u32, _vp, _vp, _vp, _vp, _vp]),
     "kron_generate_csr": (_i32, [_u32, _vp, _u32, _u64, _i32, _u64, _u32, _i32, _vp, _vp, _u32, _vp, _vp, _vp, _vp,
                                  _vp, _sz, _vp]),
     "graph_stats_workspace_bytes": (_sz, [_u64, _u64, _i32]),
@@ -250,6 +252,27 @@ def edges_to_csr(n, src, dst, *, flags=0, want_hist=True, want_dups=True, row_pt
         ws = workspace(need, src.device)
     _check(lib.edges_to_csr(n, E, _ptr(src), _ptr(dst), id_bytes, flags, _ptr(row_ptr), _ptr(col), _ptr(hist),
                             _ptr(dups), _ptr(ws), ws.numel(), _stream(stream)))
+    return row_ptr, col, hist, dups
+
+
+def edges_to_csr_noalloc(n, src, dst, *, flags=0, want_hist=True, want_dups=True, row_ptr=None, col=None,
+                         stream=None):
+    """edges_to_csr with the library's static scratch array as its workspace
+    (no device allocation inside the call when row_ptr and col are given);
+    returns (row_ptr, col, hist32 or None, dups tensor or None)."""
+    _require_cuda()
+    lib = load()
+    assert src.dtype == dst.dtype and src.numel() == dst.numel()
+    E = src.numel()
+    N = 2 * E if flags & CSR_SYMMETRIZE else E
+    if row_ptr is None:
+        row_ptr = torch.empty(n + 1, dtype=torch.int64, device=src.device)
+    if col is None:
+        col = torch.empty(max(N, 1), dtype=src.dtype, device=src.device)
+    hist = torch.empty(32, dtype=torch.int64, device=src.device) if want_hist else None
+    dups = torch.empty(1, dtype=torch.int64, device=src.device) if want_dups else None
+    _check(lib.edges_to_csr_noalloc(n, E, _ptr(src), _ptr(dst), src.element_size(), flags, _ptr(row_ptr), _ptr(col),
+                                    _ptr(hist), _ptr(dups), _stream(stream)))
     return row_ptr, col, hist, dups
 
 
