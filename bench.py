@@ -101,21 +101,92 @@ def _host_info():
     return {"cpu": model, "usable_cores": cores, "ram_gib": ram}
 
 
-def _cpu_baseline(cfg, sample_edges):
-    """The oracle on the first `sample_edges` edges of the workload: sampling
-    plus CSR of that sample, single-threaded; scaled to edges/s."""
+class _OneCore:
+    """Pins the calling thread (the one that runs the oracle) to one host core
+    for the duration of a with-block and restores its affinity after."""
+
+    def __enter__(self):
+        self.saved = os.sched_getaffinity(0) if hasattr(os, "sched_getaffinity") else None
+        self.core = min(self.saved) if self.saved else None
+        if self.saved:
+            os.sched_setaffinity(0, {self.core})
+        return self
+
+    def __exit__(self, *exc):
+        if self.saved:
+            os.sched_setaffinity(0, self.saved)
+        return False
+
+
+def _oracle_config_times(wl, full_cfg3):
+    """The oracle on the test configurations, each in full: PBA n = 65,536
+    (generation + symmetrized CSR), Kronecker 2x2 at 20 levels (2^24 edges,
+    generation + directed CSR with duplicate count), and -- with full_cfg3 --
+    PBA at 2^27 vertices, p = 0.1 (generation + symmetrized CSR + degree
+    histogram)."""
     import oracle
+    out = {}
+
+    def pba(c):
+        t0 = time.perf_counter()
+        src, dst = oracle.pba_generate(c["n"], c["m"], c["num_parts"], c["p_inter"], c["seed"])
+        t1 = time.perf_counter()
+        oracle.edges_to_csr(c["n"], src, dst, symmetrize=True)
+        oracle.degree_histogram(c["n"], src, dst)
+        t2 = time.perf_counter()
+        E = c["n"] * c["m"]
+        return {"edges": E, "gen_s": t1 - t0, "csr_s": t2 - t1, "edges_per_s": E / (t2 - t0)}
+
+    out[wl.PBA_SMALL["name"]] = pba(wl.PBA_SMALL)
+    c = wl.KRON_K20
     t0 = time.perf_counter()
-    src, dst = oracle.kron_sample(cfg["n0"], cfg["initiator"], cfg["k"], sample_edges, cfg["seed"])
+    src, dst = oracle.kron_sample(c["n0"], c["initiator"], c["k"], c["num_edges"], c["seed"])
     t1 = time.perf_counter()
-    n = cfg["n0"] ** cfg["k"]
-    oracle.edges_to_csr(n, src, dst)
-    oracle.degree_histogram(n, src, dst)
+    oracle.edges_to_csr(c["n0"] ** c["k"], src, dst)
     t2 = time.perf_counter()
-    return {"value": sample_edges / (t2 - t0), "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {sample_edges} edges of the workload: oracle Kronecker sampling ({t1 - t0:.1f} s) "
-                      f"+ CSR sort and degree histogram ({t2 - t1:.1f} s), single thread",
-            "host": _host_info()}
+    out[c["name"]] = {"edges": c["num_edges"], "gen_s": t1 - t0, "csr_s": t2 - t1,
+                      "edges_per_s": c["num_edges"] / (t2 - t0)}
+    del src, dst
+    if full_cfg3:
+        out[wl.PBA_SCALE[1]["name"]] = pba(wl.PBA_SCALE[1])
+    return out
+
+
+def _cpu_baseline(cfg, sample_edges, wl=None, full_cfg3=False):
+    """The oracle, pinned to one host core, on the first `sample_edges` edges
+    of the workload: sampling plus CSR of that sample; scaled to edges/s.
+    Beside it, the oracle's times on the small configurations in full."""
+    import numpy as np
+    import oracle
+    n = cfg["n0"] ** cfg["k"]
+    with _OneCore() as pin:
+        t0 = time.perf_counter()
+        src, dst = oracle.kron_sample(cfg["n0"], cfg["initiator"], cfg["k"], sample_edges, cfg["seed"])
+        t1 = time.perf_counter()
+        oracle.edges_to_csr(n, src, dst)
+        oracle.degree_histogram(n, src, dst)
+        t2 = time.perf_counter()
+        del src, dst
+        # the per-vertex part of the CSR and histogram (row starts and degrees
+        # of all n vertices), paid once per graph whatever its edge count
+        none = np.zeros(0, np.int64)
+        t3 = time.perf_counter()
+        oracle.edges_to_csr(n, none, none)
+        oracle.degree_histogram(n, none, none)
+        t_vertex = time.perf_counter() - t3
+        configs = _oracle_config_times(wl, full_cfg3) if wl is not None else None
+        pinned = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    per_edge = max(t2 - t0 - t_vertex, 1e-9) / sample_edges
+    E = cfg["num_edges"]
+    out = {"value": E / (t_vertex + per_edge * E), "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {sample_edges} edges of the workload: oracle Kronecker sampling ({t1 - t0:.1f} s) "
+                     f"+ CSR sort and degree histogram ({t2 - t1:.1f} s, of which {t_vertex:.1f} s is the "
+                     f"per-vertex part over all {n} vertices), one thread pinned to host core {pin.core}; value = "
+                     f"all {E} edges over (per-vertex time + sample time per edge x {E})",
+           "sample_edges_per_s": sample_edges / (t2 - t0), "pinned_cores": pinned, "host": _host_info()}
+    if configs is not None:
+        out["configs"] = configs
+    return out
 
 
 def main():
@@ -125,10 +196,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--cpu-sample", type=int, default=1 << 25, help="edges in the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="also time the oracle on the 2^27-vertex PBA configuration in full (minutes)")
     ap.add_argument("--no-extras", action="store_true", help="skip the PBA and ensemble extras")
-    ap.add_argument("--only", choices=("pba",), default=None,
+    ap.add_argument("--only", choices=("pba", "cpu", "surrogate"), default=None,
                     help="run only one part and print its JSON: 'pba' = PBA generation at 2^27 and 2^30 vertices "
-                         "with per-kernel times (for profiling runs)")
+                         "with per-kernel times (for profiling runs); 'cpu' = the CPU oracle baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy three times (the reference kernel of known "
                          "size for scaling the HBM byte counters) and exit")
@@ -142,6 +215,18 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read_per_copy": a.numel() * 8,
                           "bytes_written_per_copy": a.numel() * 8, "copies": 3}), flush=True)
+        return
+    if args.only == "cpu":
+        from paper_1003_3684_amd import workloads as wl
+        print(json.dumps({"cpu_baseline": _cpu_baseline(wl.KRON_SCALE, args.cpu_sample, wl, args.cpu_full)}),
+              flush=True)
+        return
+    if args.only == "surrogate":
+        import torch
+        from paper_1003_3684_amd import native as sfg
+        from paper_1003_3684_amd import workloads as wl
+        sfg.load()
+        print(json.dumps({"surrogate": _bench_surrogate(sfg, wl, torch)}), flush=True)
         return
     if args.only == "pba":
         import torch
@@ -286,14 +371,14 @@ def main():
         result["extras"] = {"pba": _bench_pba(sfg, wl, torch), "pba_paper_scale": _bench_pba_paper(sfg, wl, torch),
                             "ensemble": _bench_ensemble(sfg, wl, torch),
                             "kron_enumerate": _bench_enumerate(sfg, wl, torch),
-                            "randomized_pk": _bench_randomized_pk(sfg, wl, torch), "mlp": _bench_mlp(sfg, torch)}
+                            "randomized_pk": _bench_randomized_pk(sfg, wl, torch), "mlp": _bench_mlp(sfg, torch),
+                            "surrogate": _bench_surrogate(sfg, wl, torch)}
     if not args.no_cpu_baseline:
-        result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_sample)
+        result["cpu_baseline"] = _cpu_baseline(cfg, args.cpu_sample, wl, full_cfg3=args.cpu_full)
     print(json.dumps(result), flush=True)
 
 
-PBA_KERNELS = ("pba_draw1", "pba_resolve", "pba_tile_table", "pba_count", "pba_scan", "pba_draw2",
-               "pba_substitute", "fill")
+PBA_KERNELS = ("pba_fill", "pba_resolve", "pba_tile_table", "pba_count", "pba_scan", "pba_substitute")
 
 
 def _pba_breakdown(sfg, gen, reps):
@@ -526,13 +611,28 @@ def _bench_mlp(sfg, torch, batch=4096, steps=50):
                     "256-wide network at batch 4,096 is latency-bound, far below the matrix-core roofline"}
 
 
+def _bench_surrogate(sfg, wl, torch, graphs=100_000):
+    """The surrogate trained on `graphs` graphs of the ensemble recipe (made
+    by ensemble_generate) and inverted for the exponents 2.1 .. 3.0 on the
+    2x2 Kronecker family at 14 levels: generator runs and seconds per target,
+    with the surrogate-guided search and with the generator-only search, each
+    answer judged by the generator."""
+    from paper_1003_3684_amd import surrogate as sg
+    res = sg.ensemble_study(wl.ensemble_table(graphs, seed=19))
+    res["workload"] = f"ensemble_recipe_{graphs}_graphs_seed19"
+    torch.cuda.empty_cache()
+    return res
+
+
 def _bench_ensemble(sfg, wl, torch, samples=10_000, stat_seed=5,
                     candidates=(1 << 26, 1 << 27, 1 << 28, 1 << 30)):
     """Graphs/s of the batched ensemble entry point against the same 4,096
     graphs made one by one (generator call, then the statistics call), with
-    the statistics compared member by member.  The batch budget is chosen
-    first by the autotuner over `candidates` (each runs the whole table once;
-    the tuner checks that all give the same statistics)."""
+    the statistics compared member by member.  The tuning (batch budget, tile
+    size, persistent grid) is chosen first by the autotuner (each candidate
+    runs the whole table; the tuner checks that all give the same
+    statistics); the batched run is the captured graph of the batch sequence,
+    replayed, and the same tuning enqueued without a graph is timed beside it."""
     import numpy as np
     from paper_1003_3684_amd import tune
     rows = wl.ensemble_table()
@@ -546,18 +646,22 @@ def _bench_ensemble(sfg, wl, torch, samples=10_000, stat_seed=5,
            torch.empty(count, dtype=torch.float64, device="cuda"),
            torch.empty(count, dtype=torch.int64, device="cuda"))
     ws = sfg.workspace(sfg.ensemble_workspace_bytes(descs, max_batch_edges))
-    warm = sfg.graph_descs(rows[:64])
-    sfg.ensemble_generate(warm, num_samples=samples, stat_seed=stat_seed, max_batch_edges=max_batch_edges, ws=ws,
-                          out=tuple(t[:64] for t in out))
-    torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    sfg.ensemble_generate(descs, num_samples=samples, stat_seed=stat_seed, max_batch_edges=max_batch_edges, ws=ws,
-                          out=out)
-    b.record()
-    torch.cuda.synchronize()
-    batched_s = a.elapsed_time(b) / 1e3
-    bh, bg, bc = (t.cpu().numpy() for t in out)
+
+    def timed(graph):
+        tu = sfg.ensemble_tuning(max_batch_edges, tuned["grid_per_cu"], tuned["kron_items"], graph)
+        sfg.ensemble_generate(descs, num_samples=samples, stat_seed=stat_seed, ws=ws, out=out, tuning=tu)
+        torch.cuda.synchronize()
+        a.record()
+        sfg.ensemble_generate(descs, num_samples=samples, stat_seed=stat_seed, ws=ws, out=out, tuning=tu)
+        b.record()
+        torch.cuda.synchronize()
+        assert sfg.device_error() == 0
+        return a.elapsed_time(b) / 1e3, [t.cpu().numpy() for t in out]
+
+    eager_s, eager_out = timed(False)
+    batched_s, (bh, bg, bc) = timed(True)
+    graph_same = all(np.array_equal(x, y, equal_nan=True) for x, y in zip((bh, bg, bc), eager_out))
     del ws
     torch.cuda.empty_cache()
 
@@ -599,12 +703,17 @@ def _bench_ensemble(sfg, wl, torch, samples=10_000, stat_seed=5,
     del src, dst, pws, sws
     torch.cuda.empty_cache()
     return {"workload": f"ensemble_{count}_graphs_seed17", "graphs": count, "edges": edges,
-            "wedge_samples": samples, "max_batch_edges": max_batch_edges,
-            "tuner_seconds": {str(c): round(t, 4) for c, t in tuned["seconds"].items()},
+            "wedge_samples": samples,
+            "tuning": {"max_batch_edges": max_batch_edges, "grid_per_cu": tuned["grid_per_cu"],
+                       "kron_items": tuned["kron_items"]},
+            "tuner_seconds": {"budget": {str(c): round(t, 4) for c, t in tuned["seconds"].items()},
+                              "kron_items": {str(c): round(t, 4) for c, t in tuned["tile_seconds"].items()},
+                              "grid_per_cu": {str(c): round(t, 4) for c, t in tuned["grid_seconds"].items()}},
             "batched_s": batched_s, "batched_graphs_per_s": count / batched_s,
-            "batched_edges_per_s": edges / batched_s,
+            "batched_edges_per_s": edges / batched_s, "batched_launch": "one captured HIP graph, replayed",
+            "batched_no_graph_s": eager_s, "batched_no_graph_graphs_per_s": count / eager_s,
             "plain_s": plain_s, "plain_wall_s": plain_wall, "plain_graphs_per_s": count / plain_s,
-            "speedup": plain_s / batched_s, "stats_identical": same}
+            "speedup": plain_s / batched_s, "stats_identical": same and graph_same}
 
 
 if __name__ == "__main__":

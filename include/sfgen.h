@@ -81,8 +81,8 @@ int sfg_device_error(void *stream, uint32_t *code);
  * the stream is being captured into a graph are not timed.  Kernel names:
  * "kron_sample", "kron_enumerate", "csr_prepare", "csr_digit_bases",
  * "radix_pass", "csr_finish", "csr_rowfill", "degree_hist", "fill",
- * "pba_draw1", "pba_resolve", "pba_tile_table", "pba_count", "pba_scan",
- * "pba_draw2", "pba_substitute", "stats_chunks", "stats_gamma",
+ * "pba_fill", "pba_resolve", "pba_tile_table", "pba_count", "pba_scan",
+ * "pba_substitute", "stats_chunks", "stats_gamma",
  * "stats_wedge_scan", "stats_wedge", "path_level", "block_count",
  * "random_pairs", "perturb_expand", "mlp_gemm", "mlp_elementwise",
  * "mlp_adam". */
@@ -397,7 +397,9 @@ int block_matrix(uint64_t n, uint64_t num_edges, const void *src, const void *ds
 
 /* ------------------------------------------------------------------------
  * ensemble_generate -- a batched ensemble of graphs (PBA and Kronecker
- * members of uneven size and parameters), each summarised by graph_stats.
+ * members of uneven size and parameters), each summarised by graph_stats
+ * (the degree distributions and fitted exponents of the Results section,
+ * Fig. 3, for thousands of graphs at once).
  *
  * Member i equals the single-graph call with the same parameters and graph
  * id: pba_generate(n, m, num_parts, p_inter, NULL, NULL, seed, graph_id, ...)
@@ -405,24 +407,22 @@ int block_matrix(uint64_t n, uint64_t num_edges, const void *src, const void *ds
  * graph_id, ...), followed by graph_stats(..., num_samples, stat_seed,
  * graph_id, ...).  Its outputs go to degree_hist32[32 i .. 32 i + 31],
  * gamma[i] and closed[i] (device arrays of count entries), bit for bit the
- * single-graph results.
+ * single-graph results, whatever the tuning.
  *
  * Members are processed in batches cut greedily, in descriptor order, at
  * max_batch_edges edges or 2^24 vertices, whichever comes first (a single
  * member above either limit is a batch of its own): a batch shares one vertex
- * space and edge list, goes
- * through each generation, sort and statistics kernel once, and reuses the
- * workspace.  descs is a host array (read before the call returns; the call
- * waits for its small table uploads).  Kronecker members need n0 <= 4 and
- * n0^k <= 2^32; PBA members use the default factions.
- * workspace: device, ensemble_workspace_bytes(descs, count, max_batch_edges):
- * with more than one batch that is two halves, and consecutive batches then
- * alternate between two library streams (default priority), each with its
- * half, so that one batch's generation overlaps the other's sort; the
- * caller's stream waits for both before anything it enqueues later.  Any
- * size from one half up is accepted; below two halves the batches run one
- * after another on the caller's stream.  Results are the same either way.
- * Errors: EINVAL / ERANGE as the single-graph calls, ENOSPACE.
+ * space and edge list and goes through each generation, sort and statistics
+ * kernel once.  All batches run on `stream`, one after another.  The tables
+ * of every batch are built on the host and uploaded in one copy at the start
+ * (the call waits for it; descs is read before the call returns); the
+ * batches are then kernel launches only.  ensemble_generate uses the default
+ * tuning (grid_per_cu 8, kron_items 8, SFG_ENSEMBLE_GRAPH).
+ * Kronecker members need n0 <= 4 and n0^k <= 2^32; PBA members use the
+ * default factions.
+ * workspace: device, ensemble_workspace_bytes(descs, count, max_batch_edges).
+ * Errors: EINVAL / ERANGE as the single-graph calls, EINVAL for a bad tuning,
+ * ENOSPACE.
  * ---------------------------------------------------------------------- */
 enum { SFG_GRAPH_PBA = 0, SFG_GRAPH_KRON = 1 };
 
@@ -444,6 +444,34 @@ size_t ensemble_workspace_bytes(const sfg_graph_desc *descs, uint32_t count, uin
 int ensemble_generate(const sfg_graph_desc *descs, uint32_t count, uint32_t num_samples, uint64_t stat_seed,
                       uint64_t max_batch_edges, uint64_t *degree_hist32, double *gamma, int64_t *closed,
                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* Tuning of ensemble_generate_tuned (the choices of the autotuner; no choice
+ * changes any result):
+ *   max_batch_edges  the chunk schedule: the batch edge budget (>= 1);
+ *   grid_per_cu      workgroups per compute unit of the persistent generation
+ *                    and statistics kernels, which walk the batch's (member,
+ *                    tile) table (1 .. 64);
+ *   kron_items       edges per thread of a Kronecker sampling tile (4, 8 or
+ *                    16; a tile is 256 threads);
+ *   flags            SFG_ENSEMBLE_GRAPH: the batch sequence is captured once
+ *                    into a HIP graph (on a library stream of default
+ *                    priority) and launched on `stream` as one graph; the
+ *                    graph is cached for the same descriptors, samples, seed,
+ *                    tuning, workspace and outputs (eight per process, least
+ *                    recently used dropped), so later identical calls replay
+ *                    it.  If capture fails the sequence is enqueued directly. */
+enum { SFG_ENSEMBLE_GRAPH = 1u };
+
+typedef struct {
+    uint64_t max_batch_edges;
+    uint32_t grid_per_cu;
+    uint32_t kron_items;
+    uint32_t flags;
+} sfg_ensemble_tuning;
+
+int ensemble_generate_tuned(const sfg_graph_desc *descs, uint32_t count, uint32_t num_samples, uint64_t stat_seed,
+                            const sfg_ensemble_tuning *tuning, uint64_t *degree_hist32, double *gamma,
+                            int64_t *closed, void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * MLP surrogate -- maps generator parameters to graph statistics; trained on

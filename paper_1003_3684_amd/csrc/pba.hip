@@ -38,15 +38,13 @@
 namespace sfg {
 namespace {
 
-constexpr uint32_t kTerm = 0x80000000u;  // terminal flag of an encoded slot
+constexpr uint32_t kTerm = 0x80000000u;  // bound of a partition's slot count and of a list's length
 constexpr int kXcd = 8;
-constexpr int kDrawThreads = 256;
 constexpr int kResThreads = 256;
 constexpr int kResItems = 16;
 constexpr int kResTile = kResThreads * kResItems;  // slots per resolve tile
 constexpr int kSubThreads = 256;
 constexpr uint32_t kMaxParts = 4096;
-constexpr uint32_t kMatchParts = 1024;  // LDS lane-match tables up to this many labels
 constexpr int kScanRows = 256;
 
 // Partition boundaries floor(q n / P), evaluated without 128-bit products.
@@ -126,131 +124,86 @@ __global__ void pba_bases1(Graphs G, uint32_t S, uint64_t total, uint64_t *base1
     base1[s] = p.ebase + (uint64_t)p.m * part_start(s - p.seg0, p.n, p.P);
 }
 
-// ----------------------------------------------------------------------------- phase 1 draw
-struct Draw1Args {
-    Graphs G;
-    const uint64_t *base1;
-    uint32_t chunks;  // workgroups per segment
-    Factions f;
-    uint32_t *lab;
-};
-
-__global__ __launch_bounds__(kDrawThreads) void pba_draw1(Draw1Args a) {
-    const uint32_t s = blockIdx.x / a.chunks, c = blockIdx.x % a.chunks;
-    uint32_t g;
-    const PGraph &p = a.G.of_seg(s, g);
-    const uint32_t q = s - p.seg0;
-    const uint64_t b0 = a.base1[s], nslots = a.base1[s + 1] - b0;
-    uint32_t fs = 1, u = 1, self = q;
-    const uint32_t *F = &self, *U = &self;
-    if (a.f.foff) {
-        F = a.f.fmem + a.f.foff[q];
-        fs = a.f.foff[q + 1] - a.f.foff[q];
-        U = a.f.umem + a.f.uoff[q];
-        u = a.f.uoff[q + 1] - a.f.uoff[q];
-    }
-    const uint32_t nnf = p.P - u;
-    const uint64_t stride = (uint64_t)a.chunks * kDrawThreads;
-    for (uint64_t j = (uint64_t)c * kDrawThreads + threadIdx.x; j < nslots; j += stride) {
-        uint32_t enc;
-        if (j < fs) {
-            enc = kTerm | F[j];
-        } else {
-            const Block4 w = philox((uint32_t)j, (uint32_t)(j >> 32), q, p.tag1, p.key0, p.key1);
-            const uint64_t U64 = make_u64(w.w1, w.w2);
-            if (nnf > 0 && (uint64_t)w.w0 < p.thr_p)
-                enc = kTerm | nonfaction((uint32_t)uidx64(U64, nnf), U, u);
-            else
-                enc = (uint32_t)uidx64(U64, j);  // copy an earlier slot
-        }
-        a.lab[b0 + j] = enc;
-    }
-}
-
-// ----------------------------------------------------------------------------- phase 2 draw
-struct Draw2Args {
-    Graphs G;
-    uint32_t S;
-    uint64_t total;
-    const uint64_t *sbase;  // [S+1] list bases (prefix of D)
-    uint32_t *sel;
-};
-
-// Workgroup b draws selections [b C, (b + 1) C) (C = kDrawThreads
-// kDraw2Items) of the concatenated lists: the segment of the first is found
-// once per workgroup, and a thread moves to the next segment only when its
-// selections cross a list boundary.  Per segment the thread keeps L, D and
-// the multiply-high constant for floor(t' L / D).
-constexpr int kDraw2Items = 16;
-
-__global__ __launch_bounds__(kDrawThreads) void pba_draw2(Draw2Args a) {
-    __shared__ uint32_t s_seg;
-    const uint64_t c0 = (uint64_t)blockIdx.x * kDrawThreads * kDraw2Items;
-    if (threadIdx.x == 0) {
-        uint32_t lo = 0, hi = a.S;  // last segment s with sbase[s] <= c0
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) / 2;
-            if (a.sbase[mid] <= c0)
-                lo = mid;
-            else
-                hi = mid;
-        }
-        s_seg = lo;
-    }
-    __syncthreads();
-    uint32_t s = s_seg, g = 0, l = 0;
-    uint64_t b = 0, e = 0, D = 0, L = 0, magic = 0;
-    const PGraph *p = nullptr;
-    bool fresh = true;
-    for (int k = 0; k < kDraw2Items; ++k) {
-        const uint64_t gi = c0 + (uint64_t)k * kDrawThreads + threadIdx.x;
-        if (gi >= a.total) break;
-        while (gi >= a.sbase[s + 1]) {  // list boundary (empty lists are skipped)
-            ++s;
-            fresh = true;
-        }
-        if (fresh) {
-            p = &a.G.of_seg(s, g);
-            l = s - p->seg0;
-            b = a.sbase[s];
-            e = a.sbase[s + 1];
-            D = e - b;
-            L = part_start(l + 1, p->n, p->P) - part_start(l, p->n, p->P);
-            magic = ~0ull / D;
-            fresh = false;
-        }
-        const uint64_t t = gi - b;
-        const Block4 w = philox((uint32_t)t, (uint32_t)(t >> 32), l, p->tag2, p->key0, p->key1);
-        // Pool entry r of the first 2 + 2t: the seed clique (0, 1), an arrival
-        // vertex floor(t' L / D) at even r, or the endpoint of selection t' at odd r.
-        const uint64_t r = uidx64(make_u64(w.w0, w.w1), 2 + 2 * t);
-        uint32_t enc;
-        if (r < 2) {
-            enc = kTerm | (uint32_t)r;
-        } else if ((r & 1) == 0) {
-            const uint64_t tp = (r - 2) >> 1;
-            enc = kTerm | (uint32_t)div_magic64(tp * L, D, magic);
-        } else {
-            enc = (uint32_t)((r - 3) >> 1);
-        }
-        a.sel[gi] = enc;
-    }
+// ----------------------------------------------------------------------------- sentinels
+__global__ void pba_fill32(uint32_t *p, uint64_t n, uint32_t v) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
 // ----------------------------------------------------------------------------- chain resolution
-// Segment s spans enc[base[s] .. base[s+1]); pointers are segment-local.
-// Tiles of segment s are queued on XCD s mod 8, segment by segment, in order.
+// A slot's phase-1 label and a selection's phase-2 endpoint are found by
+// following copy pointers to a terminal draw.  Both passes run the draws
+// themselves (Philox is counter-based, so any slot's draw can be recomputed
+// anywhere): a thread draws its element, and while the draw points to an
+// earlier element it reads that element's resolved value, or, if that one is
+// not resolved yet (it still holds the sentinel every element starts from),
+// draws it in turn.  Every pointer goes to a strictly earlier element, so a
+// walk ends.  Segment s spans [base[s], base[s+1]) of the value array; tiles
+// of segment s are queued on XCD s mod 8, segment by segment, in order, so
+// most pointers land in the already resolved prefix of the segment, which
+// stays in that XCD's L2 and the memory-side cache.
+constexpr uint16_t kLabNone = 0xFFFFu;      // phase-1 label not resolved yet
+constexpr uint32_t kSelNone = 0xFFFFFFFFu;  // phase-2 endpoint not resolved yet
+
 struct ResolveArgs {
-    uint32_t *enc;
+    Graphs G;
+    Factions f;
+    void *val;                // uint16_t labels (phase 1) or uint32_t endpoints (phase 2)
     const uint64_t *base;     // [S+1]
     const uint64_t *xprefix;  // [8][xstride] tile prefix per XCD queue
     const uint64_t *xtotal;   // [8]
     uint32_t *queues;         // [8] tile tickets
-    uint32_t *err;
     uint32_t S, xstride;
 };
 
-__global__ __launch_bounds__(kResThreads) void pba_resolve(ResolveArgs a) {
+// Phase-1 parameters of one partition (workgroup-uniform).  F and U are
+// null for the default faction list [q].
+struct Seg1 {
+    uint32_t q, fs, u, nnf, tag, key0, key1;
+    uint64_t thr_p;
+    const uint32_t *F, *U;
+};
+
+// Terminal label of slot j of partition sg.q (labels: uint16_t, kLabNone
+// while unresolved).
+__device__ __forceinline__ uint32_t phase1_label(uint64_t j, const Seg1 &sg, const uint16_t *lab) {
+    for (;;) {
+        if (j < sg.fs) return sg.F ? sg.F[j] : sg.q;
+        const Block4 w = philox((uint32_t)j, (uint32_t)(j >> 32), sg.q, sg.tag, sg.key0, sg.key1);
+        const uint64_t U64 = make_u64(w.w1, w.w2);
+        if (sg.nnf > 0 && (uint64_t)w.w0 < sg.thr_p) {
+            const uint32_t r = (uint32_t)uidx64(U64, sg.nnf);
+            return sg.U ? nonfaction(r, sg.U, sg.u) : r + (r >= sg.q ? 1u : 0u);
+        }
+        j = uidx64(U64, j);  // copy an earlier slot
+        const uint32_t v = lab[j];
+        if (v != kLabNone) return v;
+    }
+}
+
+// Phase-2 parameters of one list (workgroup-uniform).
+struct Seg2 {
+    uint32_t l, tag, key0, key1;
+    uint64_t L, D, magic;
+};
+
+// Endpoint (local vertex) of selection t of list sg.l: pool entry r of the
+// first 2 + 2t is a seed-clique vertex (r < 2), the arrival floor(t' L / D)
+// of selection t' = (r - 2) / 2 (even r), or the endpoint of selection
+// (r - 3) / 2 (odd r).
+__device__ __forceinline__ uint32_t phase2_endpoint(uint64_t t, const Seg2 &sg, const uint32_t *sel) {
+    for (;;) {
+        const Block4 w = philox((uint32_t)t, (uint32_t)(t >> 32), sg.l, sg.tag, sg.key0, sg.key1);
+        const uint64_t r = uidx64(make_u64(w.w0, w.w1), 2 + 2 * t);
+        if (r < 2) return (uint32_t)r;
+        if ((r & 1) == 0) return (uint32_t)div_magic64(((r - 2) >> 1) * sg.L, sg.D, sg.magic);
+        t = (r - 3) >> 1;
+        const uint32_t v = sel[t];
+        if (v != kSelNone) return v;
+    }
+}
+
+template <int PHASE> __global__ __launch_bounds__(kResThreads) void pba_resolve(ResolveArgs a) {
     __shared__ uint64_t s_tile;
     __shared__ uint32_t s_seg;
     const int tid = threadIdx.x;
@@ -282,31 +235,49 @@ __global__ __launch_bounds__(kResThreads) void pba_resolve(ResolveArgs a) {
             const uint32_t i = s_seg;
             __syncthreads();
             if (t >= total) break;
-            const uint32_t sg = x + kXcd * i;
-            const uint64_t b0 = a.base[sg];
-            const uint64_t len = a.base[sg + 1] - b0;
+            const uint32_t sgi = x + kXcd * i;
+            const uint64_t b0 = a.base[sgi];
+            const uint64_t len = a.base[sgi + 1] - b0;
             const uint64_t first = (t - pre[i]) * kResTile;
-            uint32_t *seg = a.enc + b0;
-#pragma unroll
-            for (int k = 0; k < kResItems; ++k) {
-                const uint64_t j = first + (uint64_t)k * kResThreads + tid;
-                if (j < len) {
-                    uint32_t v = seg[j];
-                    if (!(v & kTerm)) {
-                        // Every hop goes to a strictly earlier slot; a value that
-                        // does not is corrupt and ends the walk.
-                        uint64_t cur = j;
-                        while (!(v & kTerm)) {
-                            if ((uint64_t)v >= cur) {
-                                raise_device_error(a.err, DEVERR_CHAIN);
-                                v = kTerm;
-                                break;
-                            }
-                            cur = v;
-                            v = seg[v];
-                        }
-                        seg[j] = v;
-                    }
+            uint32_t g;
+            const PGraph &p = a.G.of_seg(sgi, g);
+            if (PHASE == 1) {
+                Seg1 sg;
+                sg.q = sgi - p.seg0;
+                sg.fs = 1;
+                sg.u = 1;
+                sg.F = sg.U = nullptr;
+                if (a.f.foff) {
+                    sg.F = a.f.fmem + a.f.foff[sg.q];
+                    sg.fs = a.f.foff[sg.q + 1] - a.f.foff[sg.q];
+                    sg.U = a.f.umem + a.f.uoff[sg.q];
+                    sg.u = a.f.uoff[sg.q + 1] - a.f.uoff[sg.q];
+                }
+                sg.nnf = p.P - sg.u;
+                sg.thr_p = p.thr_p;
+                sg.tag = p.tag1;
+                sg.key0 = p.key0;
+                sg.key1 = p.key1;
+                uint16_t *lab = static_cast<uint16_t *>(a.val) + b0;
+#pragma unroll 4
+                for (int k = 0; k < kResItems; ++k) {
+                    const uint64_t j = first + (uint64_t)k * kResThreads + tid;
+                    if (j < len) lab[j] = (uint16_t)phase1_label(j, sg, lab);
+                }
+            } else {
+                Seg2 sg;
+                sg.l = sgi - p.seg0;
+                sg.tag = p.tag2;
+                sg.key0 = p.key0;
+                sg.key1 = p.key1;
+                sg.L = part_start(sg.l + 1, p.n, p.P) - part_start(sg.l, p.n, p.P);
+                sg.D = len;
+                sg.magic = len ? ~0ull / len : 0;
+                uint32_t *sel = static_cast<uint32_t *>(a.val) + b0;
+#pragma unroll 4
+                for (int k = 0; k < kResItems; ++k) {
+                    const uint64_t tt = first + (uint64_t)k * kResThreads + tid;
+                    if (tt < len) sel[tt] = phase2_endpoint(tt, sg, sel);
                 }
             }
         }
@@ -354,7 +325,7 @@ __global__ __launch_bounds__(1024) void pba_tile_table(const uint64_t *base, uin
 // q; its label histogram is row H0 + (q * T1 + tau) of P columns.
 struct CountArgs {
     Graphs G;
-    const uint32_t *lab;
+    const uint16_t *lab;
     const uint64_t *base1;
     uint32_t *H;
     uint32_t T1max;
@@ -372,7 +343,7 @@ __global__ __launch_bounds__(256) void pba_count(CountArgs a) {
     const uint64_t b0 = a.base1[s], len = a.base1[s + 1] - b0;
     const uint64_t first = (uint64_t)tau * p.CT;
     const uint64_t last = std::min<uint64_t>(len, first + p.CT);
-    for (uint64_t j = first + threadIdx.x; j < last; j += 256) atomicAdd(&s_h[a.lab[b0 + j] & ~kTerm], 1u);
+    for (uint64_t j = first + threadIdx.x; j < last; j += 256) atomicAdd(&s_h[a.lab[b0 + j]], 1u);
     __syncthreads();
     uint32_t *row = a.H + p.H0 + ((uint64_t)q * p.T1 + tau) * p.P;
     for (uint32_t l = threadIdx.x; l < p.P; l += 256) row[l] = s_h[l];
@@ -461,65 +432,71 @@ __global__ __launch_bounds__(1024) void pba_list_bases(const uint64_t *D, uint32
 }
 
 // ----------------------------------------------------------------------------- substitution
-// Tile (q, tau) of CT slots: 4 waves each walk a contiguous quarter in slot
-// order.  The k-th occurrence of label l in the tile takes endpoint
-// H[q,tau][l] + k of l's list (H holds the exclusive column prefix).  Lanes of
-// one 64-slot step that share a label are found through an LDS lane-match
-// table (MATCH, up to kMatchParts labels) or by ballots over the label bits.
+// Tile (q, tau) of CT slots, taken in sub-tiles of kSubSlots slots in slot
+// order.  The k-th slot of label l in the tile takes entry H[q,tau][l] + k of
+// l's list (H holds the exclusive column prefix).  Each sub-tile is sorted by
+// label in LDS -- stable ranks inside each wave's quarter from ballots over
+// the label bits, then prefixes over the waves and over the labels (lane-match
+// tables in LDS were slower: their 32 KB cost a workgroup per CU) -- so that one label's
+// run of endpoints is loaded by consecutive lanes from consecutive addresses
+// (one request per run instead of one per slot); the edges are then written
+// in slot order.  Tiles are spread over the XCDs in contiguous ranges
+// (workgroup b runs on XCD b mod 8), so neighbouring tiles of a partition,
+// which read neighbouring pieces of the same lists, share an L2.
+constexpr int kSubSlots = 2048;
+constexpr int kSubWave = kSubSlots / 4;  // slots of each wave's quarter
+constexpr int kSubSteps = kSubWave / 64;
+static_assert(kSubThreads == 256, "four waves per substitution workgroup");
+
 struct SubArgs {
     Graphs G;
-    const uint32_t *lab;
+    const uint16_t *lab;
     const uint64_t *base1;
     const uint32_t *H;
     const uint64_t *sbase;
     const uint32_t *sel;
     void *src, *dst;
     uint32_t T1max, Pmax;
+    uint64_t tiles, per_xcd;
 };
 
-template <typename IdT, bool MATCH> __global__ __launch_bounds__(kSubThreads) void pba_substitute(SubArgs a) {
-    extern __shared__ uint64_t s_dyn[];  // MATCH: [4][Pmax] masks, then [4][Pmax] counters
-    const uint32_t s = blockIdx.x / a.T1max, tau = blockIdx.x % a.T1max;
+// Bytes of dynamic LDS of the substitution for up to Pmax labels.
+size_t sub_lds_bytes(uint32_t Pmax) {
+    return (size_t)Pmax * 8 + (size_t)kSubSlots * 4 + (size_t)4 * Pmax * 2 + (size_t)Pmax * 2 + (size_t)kSubSlots * 2 * 2;
+}
+
+template <typename IdT> __global__ __launch_bounds__(kSubThreads) void pba_substitute(SubArgs a) {
+    extern __shared__ uint64_t s_dyn[];
+    __shared__ uint32_t s_part[kSubThreads / 64];
+    const uint64_t b = blockIdx.x;
+    const uint64_t lt = (b % kXcd) * a.per_xcd + b / kXcd;
+    if (lt >= a.tiles) return;
+    const uint32_t s = (uint32_t)(lt / a.T1max), tau = (uint32_t)(lt % a.T1max);
     uint32_t g;
     const PGraph &p = a.G.of_seg(s, g);
     if (tau >= p.T1) return;
     const uint32_t q = s - p.seg0;
+    const uint32_t P = p.P, Pm = a.Pmax;
     const int tid = threadIdx.x, w = tid >> 6;
     const uint32_t lane = tid & 63;
-    const uint32_t P = p.P;
-    uint64_t *s_match = s_dyn;
-    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(s_dyn + (MATCH ? 4 * a.Pmax : 0));
-    for (uint32_t i = tid; i < 4 * P; i += kSubThreads) {
-        s_cnt[i] = 0;
-        if (MATCH) s_match[i] = 0;
-    }
-    __syncthreads();
+    // LDS carving (8-byte arrays first).
+    uint64_t *s_cur = s_dyn;                                      // [Pm] next list entry of each label
+    uint32_t *s_val = reinterpret_cast<uint32_t *>(s_cur + Pm);   // [kSubSlots] endpoints, slot order
+    uint16_t *s_wcnt = reinterpret_cast<uint16_t *>(s_val + kSubSlots);  // [4][Pm]
+    uint16_t *s_off = s_wcnt + 4 * Pm;                            // [Pm] label bases in sorted order
+    uint16_t *s_lab = s_off + Pm;                                 // [kSubSlots] labels, slot order
+    uint16_t *s_perm = s_lab + kSubSlots;                         // [kSubSlots] slot of each sorted position
+
     const uint64_t b0 = a.base1[s], len = a.base1[s + 1] - b0;
     const uint64_t first = (uint64_t)tau * p.CT;
     const uint64_t last = std::min<uint64_t>(len, first + p.CT);
-    const uint32_t quarter = p.CT / 4;
-    const uint64_t wfirst = first + (uint64_t)w * quarter;
-    const uint64_t wlast = std::min<uint64_t>(last, wfirst + quarter);
-    uint32_t *cnt = s_cnt + (uint64_t)w * P;
-    uint64_t *match = s_match + (uint64_t)w * P;
-    // Pass 1: per-wave label counts.
-    for (uint64_t j = wfirst + lane; j < wlast; j += 64) atomicAdd(&cnt[a.lab[b0 + j] & ~kTerm], 1u);
-    __syncthreads();
-    // Per label: start of each wave's run inside the tile's share of the list.
     const uint32_t *hrow = a.H + p.H0 + ((uint64_t)q * p.T1 + tau) * P;
-    for (uint32_t l = tid; l < P; l += kSubThreads) {
-        uint32_t acc = hrow[l];
-        for (int wv = 0; wv < 4; ++wv) {
-            const uint32_t c = s_cnt[wv * P + l];
-            s_cnt[wv * P + l] = acc;
-            acc += c;
-        }
-    }
+    const uint64_t *lbase = a.sbase + p.seg0;
+    for (uint32_t l = tid; l < P; l += kSubThreads) s_cur[l] = lbase[l] + hrow[l];
     __syncthreads();
-    // Pass 2: slots in order.
     uint32_t lbits = 0;
     while ((1u << lbits) < P) ++lbits;
-    const uint64_t vstart = p.vbase + part_start(q, p.n, p.P);
+    const uint64_t vstart = p.vbase + part_start(q, p.n, P);
     // Per-element divisions by multiply-high: start(l) = l floor(n / P) +
     // floor(l (n mod P) / P) with l (n mod P) < P^2 <= 2^24, and the local
     // source j / m with j below the partition's slot count (< 2^31, checked
@@ -527,40 +504,121 @@ template <typename IdT, bool MATCH> __global__ __launch_bounds__(kSubThreads) vo
     const uint64_t pq = p.n / P;
     const uint32_t pr = (uint32_t)(p.n % P), pmagic = 0xFFFFFFFFu / P, mmagic = 0xFFFFFFFFu / p.m;
     IdT *src = static_cast<IdT *>(a.src), *dst = static_cast<IdT *>(a.dst);
-    const uint64_t *lbase = a.sbase + p.seg0;
-    for (uint64_t j0 = wfirst; j0 < wlast; j0 += 64) {
-        const uint64_t j = j0 + lane;
-        const bool valid = j < wlast;
-        const uint32_t l = valid ? (a.lab[b0 + j] & ~kTerm) : 0;
-        uint64_t peers;
-        if (MATCH) {
-            if (valid) atomicOr(reinterpret_cast<unsigned long long *>(&match[l]), 1ull << lane);
+    uint16_t *wcnt = s_wcnt + (uint64_t)w * Pm;
+
+    for (uint64_t pos0 = first; pos0 < last; pos0 += kSubSlots) {
+        const uint32_t nsub = (uint32_t)std::min<uint64_t>(kSubSlots, last - pos0);
+        for (uint32_t l = lane; l < P; l += 64) wcnt[l] = 0;
+        // Labels of this wave's quarter, and their stable ranks inside it.
+        uint32_t lr[kSubSteps], rr[kSubSteps];
+#pragma unroll
+        for (int st = 0; st < kSubSteps; ++st) {
+            const uint32_t i = (uint32_t)w * kSubWave + (uint32_t)st * 64 + lane;
+            const bool valid = i < nsub;
+            const uint32_t l = valid ? a.lab[b0 + pos0 + i] : 0u;
+            if (valid) s_lab[i] = (uint16_t)l;
+            lr[st] = l;
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int st = 0; st < kSubSteps; ++st) {
+            const uint32_t i = (uint32_t)w * kSubWave + (uint32_t)st * 64 + lane;
+            const bool valid = i < nsub;
+            const uint32_t l = lr[st];
+            // The lanes holding the same label: every ballot over one label
+            // bit keeps the lanes that agree with this lane on that bit.
+            uint64_t peers = __ballot(valid);
+            for (uint32_t bb = 0; bb < lbits; ++bb) {
+                const bool bit = (l >> bb) & 1u;
+                const uint64_t m = __ballot(bit);
+                peers &= bit ? m : ~m;
+            }
+            if (!valid) peers = 0;
+            const uint32_t below = count_below(peers);
+            const uint32_t k = wcnt[l];
+            rr[st] = k + below;
             __builtin_amdgcn_wave_barrier();
-            peers = valid ? match[l] : 0ull;
-        } else {
-            peers = __ballot(valid);
-            for (uint32_t b = 0; b < lbits; ++b) {
-                const bool bit = (l >> b) & 1u;
-                const uint64_t bb = __ballot(bit);
-                peers &= bit ? bb : ~bb;
+            if (valid && below == 0) wcnt[l] = (uint16_t)(k + (uint32_t)__popcll(peers));
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        // Per label: prefix over the waves; then the label bases of the
+        // sorted order by a block scan over the labels (contiguous ranges of
+        // labels per thread).
+        const uint32_t per = (P + kSubThreads - 1) / kSubThreads;
+        const uint32_t l0 = (uint32_t)tid * per, l1 = std::min<uint32_t>(P, l0 + per);
+        uint32_t tsum = 0;
+        for (uint32_t l = l0; l < l1; ++l) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int wv = 0; wv < 4; ++wv) {
+                const uint32_t c = s_wcnt[wv * Pm + l];
+                s_wcnt[wv * Pm + l] = (uint16_t)acc;
+                acc += c;
+            }
+            s_off[l] = (uint16_t)acc;  // the label's count, for now
+            tsum += acc;
+        }
+        uint32_t x = tsum;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(x, off, 64);
+            if (lane >= (uint32_t)off) x += y;
+        }
+        if (lane == 63) s_part[w] = x;
+        __syncthreads();
+        uint32_t run = x - tsum;
+        for (int wv = 0; wv < w; ++wv) run += s_part[wv];
+        for (uint32_t l = l0; l < l1; ++l) {
+            const uint32_t c = s_off[l];
+            s_off[l] = (uint16_t)run;
+            run += c;
+        }
+        __syncthreads();
+        // Sorted position of every slot.
+#pragma unroll
+        for (int st = 0; st < kSubSteps; ++st) {
+            const uint32_t i = (uint32_t)w * kSubWave + (uint32_t)st * 64 + lane;
+            if (i < nsub) {
+                const uint32_t l = lr[st];
+                s_perm[s_off[l] + s_wcnt[w * Pm + l] + rr[st]] = (uint16_t)i;
             }
         }
-        const uint32_t below = count_below(peers);
-        const uint32_t k = cnt[l];
-        __builtin_amdgcn_wave_barrier();
-        if (valid && below == 0) {
-            cnt[l] = k + (uint32_t)__popcll(peers);
-            if (MATCH) match[l] = 0;
+        __syncthreads();
+        // Gather in sorted order: the lanes of one label's run read
+        // consecutive list entries.  All of a thread's loads are issued
+        // before any result is stored, so they are in flight together.
+        {
+            constexpr int kPerThread = kSubSlots / kSubThreads;
+            uint32_t slot[kPerThread], v[kPerThread];
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k) {
+                const uint32_t i = (uint32_t)k * kSubThreads + tid;
+                slot[k] = i < nsub ? s_perm[i] : 0u;
+                const uint32_t l = s_lab[slot[k]];
+                v[k] = i < nsub ? a.sel[s_cur[l] + (i - s_off[l])] : 0u;
+            }
+#pragma unroll
+            for (int k = 0; k < kPerThread; ++k)
+                if ((uint32_t)k * kSubThreads + tid < nsub) s_val[slot[k]] = v[k];
         }
-        if (valid) {
-            const uint64_t y = a.sel[lbase[l] + k + below] & ~kTerm;
+        __syncthreads();
+        // Edges in slot order.
+        for (uint32_t i = tid; i < nsub; i += kSubThreads) {
+            const uint64_t j = pos0 + i;
+            const uint32_t l = s_lab[i];
             const uint64_t e = b0 + j;
             const uint64_t jm = div_magic32((uint32_t)j, p.m, mmagic);
             const uint64_t lstart = (uint64_t)l * pq + div_magic32(l * pr, P, pmagic);
             src[e] = (IdT)(vstart + jm);
-            dst[e] = (IdT)(p.vbase + lstart + y);
+            dst[e] = (IdT)(p.vbase + lstart + s_val[i]);
         }
-        __builtin_amdgcn_wave_barrier();
+        // Advance every label's list position by its count in this sub-tile.
+        for (uint32_t l = tid; l < P; l += kSubThreads) {
+            const uint32_t nxt = l + 1 < P ? s_off[l + 1] : nsub;
+            s_cur[l] += nxt - s_off[l];
+        }
+        __syncthreads();
     }
 }
 
@@ -581,7 +639,7 @@ struct PbaPlan {
     uint64_t E, Htotal, groups;
     bool grouped;  // one large graph: three-step column scan
     size_t off_lab, off_sel, off_H, off_part, off_base1, off_sbase, off_D, off_xpre, off_xtot, off_queues, off_foff,
-        off_fmem, off_uoff, off_umem, off_table, off_seg, total;
+        off_fmem, off_uoff, off_umem, total;
 };
 
 static PbaPlan plan_batch(const PbaGraphSpec *gs, uint32_t count, uint64_t fmem_count) {
@@ -607,7 +665,7 @@ static PbaPlan plan_batch(const PbaGraphSpec *gs, uint32_t count, uint64_t fmem_
         o += align256(bytes);
         return r;
     };
-    p.off_lab = take(p.E * 4);
+    p.off_lab = take(p.E * 2);
     p.off_sel = take(p.E * 4);
     p.off_H = take(p.Htotal * 4);
     p.off_part = take(p.grouped ? p.groups * p.Pmax * 4 : 0);
@@ -621,8 +679,6 @@ static PbaPlan plan_batch(const PbaGraphSpec *gs, uint32_t count, uint64_t fmem_
     p.off_fmem = take(count == 1 ? std::max<uint64_t>(fmem_count, 1) * 4 : 0);
     p.off_uoff = take(count == 1 ? (p.S + 1) * 4 : 0);
     p.off_umem = take(count == 1 ? std::max<uint64_t>(fmem_count, 1) * 4 : 0);
-    p.off_table = take(count > 1 ? count * sizeof(PGraph) : 0);
-    p.off_seg = take(count > 1 ? p.S * 4 : 0);
     p.total = o;
     return p;
 }
@@ -646,15 +702,164 @@ int pba_check_spec(const PbaGraphSpec &g, int id_bytes, const char *who) {
     return SFG_OK;
 }
 
-int pba_run_batch(const PbaGraphSpec *gs, uint32_t count, const uint32_t *faction_off, const uint32_t *faction_members,
-                  int id_bytes, void *src, void *dst, void *workspace, size_t workspace_bytes, hipStream_t s) {
-    const char *who = count == 1 ? "pba_generate" : "ensemble_generate";
+// Device tables of a batch of more than one graph: the graph table and the
+// segment -> graph map, as one blob (built on the host, uploaded by the caller).
+static size_t tables_seg_offset(uint32_t count) { return align256((size_t)count * sizeof(PGraph)); }
+
+static void build_table(const PbaGraphSpec *gs, uint32_t count, PGraph *table, uint32_t *seg_graph) {
+    uint64_t ebase = 0, H0 = 0;
+    uint32_t seg0 = 0;
+    for (uint32_t g = 0; g < count; ++g) {
+        const PbaGraphSpec &sp = gs[g];
+        PGraph &p = table[g];
+        memset(&p, 0, sizeof(p));
+        const uint64_t Lmax = (sp.n + sp.P - 1) / sp.P;
+        p.n = sp.n;
+        p.vbase = sp.vbase;
+        p.ebase = ebase;
+        const double t = std::floor(sp.p_inter * 4294967296.0);
+        p.thr_p = t <= 0.0 ? 0 : (t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t);
+        p.m = sp.m;
+        p.P = sp.P;
+        p.CT = choose_ct(sp.P);
+        p.T1 = (uint32_t)((Lmax * sp.m + p.CT - 1) / p.CT);
+        p.H0 = H0;
+        p.seg0 = seg0;
+        p.key0 = (uint32_t)sp.seed;
+        p.key1 = (uint32_t)(sp.seed >> 32);
+        p.tag1 = TAG_PBA1 | (sp.graph_id << 8);
+        p.tag2 = TAG_PBA2 | (sp.graph_id << 8);
+        ebase += sp.n * sp.m;
+        H0 += (uint64_t)sp.P * p.T1 * sp.P;
+        if (seg_graph)
+            for (uint32_t q = 0; q < sp.P; ++q) seg_graph[seg0 + q] = g;
+        seg0 += sp.P;
+    }
+}
+
+size_t pba_tables_bytes(const PbaGraphSpec *gs, uint32_t count) {
+    if (count < 2) return 0;
+    uint64_t S = 0;
+    for (uint32_t g = 0; g < count; ++g) S += gs[g].P;
+    return tables_seg_offset(count) + align256(S * 4);
+}
+
+void pba_tables_fill(const PbaGraphSpec *gs, uint32_t count, void *host) {
+    if (count < 2) return;
+    char *h = static_cast<char *>(host);
+    build_table(gs, count, reinterpret_cast<PGraph *>(h), reinterpret_cast<uint32_t *>(h + tables_seg_offset(count)));
+}
+
+// Every pass of the generation for a planned batch, enqueued on s (kernel
+// launches only: the sequence can be captured into a graph).
+static int enqueue(const PbaPlan &pl, const Graphs &G, const Factions &fac, uint32_t count, uint32_t T1_single,
+                   uint32_t P_single, int id_bytes, void *src, void *dst, char *ws, hipStream_t s, const char *who) {
+    uint32_t *err = device_error_word();
+    if (!err) return fail(SFG_EDEVICE, "%s: no device", who);
+    uint16_t *lab = reinterpret_cast<uint16_t *>(ws + pl.off_lab);
+    uint32_t *sel = reinterpret_cast<uint32_t *>(ws + pl.off_sel);
+    uint32_t *H = reinterpret_cast<uint32_t *>(ws + pl.off_H);
+    uint32_t *part = reinterpret_cast<uint32_t *>(ws + pl.off_part);
+    uint64_t *base1 = reinterpret_cast<uint64_t *>(ws + pl.off_base1);
+    uint64_t *sbase = reinterpret_cast<uint64_t *>(ws + pl.off_sbase);
+    uint64_t *D = reinterpret_cast<uint64_t *>(ws + pl.off_D);
+    uint64_t *xpre = reinterpret_cast<uint64_t *>(ws + pl.off_xpre);
+    uint64_t *xtot = reinterpret_cast<uint64_t *>(ws + pl.off_xtot);
+    uint32_t *queues = reinterpret_cast<uint32_t *>(ws + pl.off_queues);
+    (void)count;
+    const int cus = device_cu_count();
+    const int res_grid = cus * 8;
+    const uint32_t S = pl.S;
+
+    auto fill32 = [&](void *ptr, uint64_t words, uint32_t v) {
+        if (!words) return;
+        ProfScope _ps("pba_fill", s);
+        const uint64_t want = (words + 255) / 256;
+        pba_fill32<<<(unsigned)std::min<uint64_t>(want, (uint64_t)cus * 8), 256, 0, s>>>(static_cast<uint32_t *>(ptr),
+                                                                                      words, v);
+    };
+
+    // Phase 1: every slot's label, drawn and resolved in one pass over
+    // sentinel-initialised labels.
+    { ProfScope _ps("pba_tile_table", s); pba_bases1<<<(S + 1 + 255) / 256, 256, 0, s>>>(G, S, pl.E, base1); }
+    fill32(lab, (pl.E + 1) / 2, 0xFFFFFFFFu);
+    { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<kXcd, 1024, 0, s>>>(base1, S, pl.xstride, xpre, xtot, queues); }
+    {
+        ProfScope _ps("pba_resolve", s);
+        pba_resolve<1><<<res_grid, kResThreads, 0, s>>>(ResolveArgs{G, fac, lab, base1, xpre, xtot, queues, S, pl.xstride});
+    }
+
+    // Count exchange.
+    { ProfScope _ps("pba_count", s); pba_count<<<S * pl.T1max, 256, pl.Pmax * 4, s>>>(CountArgs{G, lab, base1, H, pl.T1max}); }
+    if (pl.grouped) {
+        const uint32_t P = P_single;
+        const uint64_t R = (uint64_t)P * T1_single;
+        dim3 gsc((unsigned)pl.groups, (P + 255) / 256);
+        { ProfScope _ps("pba_scan", s); pba_scan_partial<<<gsc, 256, 0, s>>>(H, R, P, part); }
+        { ProfScope _ps("pba_scan", s); pba_scan_groups<<<(P + 255) / 256, 256, 0, s>>>(part, pl.groups, P, D, err); }
+        { ProfScope _ps("pba_scan", s); pba_scan_apply<<<gsc, 256, 0, s>>>(H, R, P, part); }
+    } else {
+        { ProfScope _ps("pba_scan", s); pba_scan_columns<<<(S + 255) / 256, 256, 0, s>>>(G, S, H, D, err); }
+    }
+    { ProfScope _ps("pba_scan", s); pba_list_bases<<<1, 1024, 0, s>>>(D, S, sbase); }
+
+    // Phase 2: every selection's endpoint, drawn and resolved in one pass.
+    fill32(sel, pl.E, kSelNone);
+    { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<kXcd, 1024, 0, s>>>(sbase, S, pl.xstride, xpre, xtot, queues + kXcd); }
+    {
+        ProfScope _ps("pba_resolve", s);
+        pba_resolve<2><<<res_grid, kResThreads, 0, s>>>(ResolveArgs{G, fac, sel, sbase, xpre, xtot, queues + kXcd, S, pl.xstride});
+    }
+
+    // Substitution.
+    const uint64_t tiles = (uint64_t)S * pl.T1max;
+    const uint64_t per_xcd = (tiles + kXcd - 1) / kXcd;
+    SubArgs sa{G, lab, base1, H, sbase, sel, src, dst, pl.T1max, pl.Pmax, tiles, per_xcd};
+    const size_t lds = sub_lds_bytes(pl.Pmax);
+    const unsigned gsub = (unsigned)(per_xcd * kXcd);
+    {
+        ProfScope _ps("pba_substitute", s);
+        if (id_bytes == 4)
+            pba_substitute<int32_t><<<gsub, kSubThreads, lds, s>>>(sa);
+        else
+            pba_substitute<int64_t><<<gsub, kSubThreads, lds, s>>>(sa);
+    }
+    return check_launch(who);
+}
+
+int pba_enqueue_batch(const PbaGraphSpec *gs, uint32_t count, int id_bytes, void *src, void *dst, void *workspace,
+                      size_t workspace_bytes, const void *dev_tables, hipStream_t s) {
+    const char *who = "ensemble_generate";
     if (count == 0) return SFG_OK;
     for (uint32_t g = 0; g < count; ++g) {
         int rc = pba_check_spec(gs[g], id_bytes, who);
         if (rc != SFG_OK) return rc;
     }
-    if (faction_off && count != 1) return fail(SFG_EINVAL, "%s: faction tables need a single graph", who);
+    const PbaPlan pl = plan_batch(gs, count, 0);
+    if (!src || !dst || !workspace || (count > 1 && !dev_tables)) return fail(SFG_EINVAL, "%s: NULL buffer", who);
+    if (workspace_bytes < pl.total)
+        return fail(SFG_ENOSPACE, "%s: workspace has %zu bytes, needs %zu", who, workspace_bytes, pl.total);
+    PGraph first;
+    build_table(gs, 1, &first, nullptr);
+    Graphs G;
+    memset(&G, 0, sizeof(G));
+    G.one = first;
+    if (count > 1) {
+        const char *t = static_cast<const char *>(dev_tables);
+        G.table = reinterpret_cast<const PGraph *>(t);
+        G.seg_graph = reinterpret_cast<const uint32_t *>(t + tables_seg_offset(count));
+    }
+    return enqueue(pl, G, Factions{nullptr, nullptr, nullptr, nullptr}, count, first.T1, first.P, id_bytes, src, dst,
+                   static_cast<char *>(workspace), s, who);
+}
+
+// One graph (pba_generate), with optional faction tables.
+int pba_run_batch(const PbaGraphSpec *gs, uint32_t count, const uint32_t *faction_off, const uint32_t *faction_members,
+                  int id_bytes, void *src, void *dst, void *workspace, size_t workspace_bytes, hipStream_t s) {
+    const char *who = "pba_generate";
+    if (count != 1) return fail(SFG_EINVAL, "%s: one graph per call", who);
+    int rc = pba_check_spec(gs[0], id_bytes, who);
+    if (rc != SFG_OK) return rc;
     // Faction tables.
     std::vector<uint32_t> foff, fmem, uoff, umem;
     if (faction_off) {
@@ -683,70 +888,16 @@ int pba_run_batch(const PbaGraphSpec *gs, uint32_t count, const uint32_t *factio
             uoff[q + 1] = (uint32_t)umem.size();
         }
     }
-    const PbaPlan pl = plan_batch(gs, count, fmem.size());
+    const PbaPlan pl = plan_batch(gs, 1, fmem.size());
     if (!src || !dst || !workspace) return fail(SFG_EINVAL, "%s: NULL buffer", who);
     if (workspace_bytes < pl.total)
         return fail(SFG_ENOSPACE, "%s: workspace has %zu bytes, needs %zu", who, workspace_bytes, pl.total);
-    uint32_t *err = device_error_word();
-    if (!err) return fail(SFG_EDEVICE, "%s: no device", who);
-
     char *ws = static_cast<char *>(workspace);
-    uint32_t *lab = reinterpret_cast<uint32_t *>(ws + pl.off_lab);
-    uint32_t *sel = reinterpret_cast<uint32_t *>(ws + pl.off_sel);
-    uint32_t *H = reinterpret_cast<uint32_t *>(ws + pl.off_H);
-    uint32_t *part = reinterpret_cast<uint32_t *>(ws + pl.off_part);
-    uint64_t *base1 = reinterpret_cast<uint64_t *>(ws + pl.off_base1);
-    uint64_t *sbase = reinterpret_cast<uint64_t *>(ws + pl.off_sbase);
-    uint64_t *D = reinterpret_cast<uint64_t *>(ws + pl.off_D);
-    uint64_t *xpre = reinterpret_cast<uint64_t *>(ws + pl.off_xpre);
-    uint64_t *xtot = reinterpret_cast<uint64_t *>(ws + pl.off_xtot);
-    uint32_t *queues = reinterpret_cast<uint32_t *>(ws + pl.off_queues);
-
-    // Graph table.
-    std::vector<PGraph> table(count);
-    std::vector<uint32_t> seg_graph;
-    uint64_t ebase = 0, H0 = 0;
-    uint32_t seg0 = 0;
-    for (uint32_t g = 0; g < count; ++g) {
-        const PbaGraphSpec &sp = gs[g];
-        PGraph &p = table[g];
-        memset(&p, 0, sizeof(p));
-        const uint64_t Lmax = (sp.n + sp.P - 1) / sp.P;
-        p.n = sp.n;
-        p.vbase = sp.vbase;
-        p.ebase = ebase;
-        const double t = std::floor(sp.p_inter * 4294967296.0);
-        p.thr_p = t <= 0.0 ? 0 : (t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t);
-        p.m = sp.m;
-        p.P = sp.P;
-        p.CT = choose_ct(sp.P);
-        p.T1 = (uint32_t)((Lmax * sp.m + p.CT - 1) / p.CT);
-        p.H0 = H0;
-        p.seg0 = seg0;
-        p.key0 = (uint32_t)sp.seed;
-        p.key1 = (uint32_t)(sp.seed >> 32);
-        p.tag1 = TAG_PBA1 | (sp.graph_id << 8);
-        p.tag2 = TAG_PBA2 | (sp.graph_id << 8);
-        ebase += sp.n * sp.m;
-        H0 += (uint64_t)sp.P * p.T1 * sp.P;
-        seg0 += sp.P;
-        if (count > 1)
-            for (uint32_t q = 0; q < sp.P; ++q) seg_graph.push_back(g);
-    }
+    PGraph first;
+    build_table(gs, 1, &first, nullptr);
     Graphs G;
     memset(&G, 0, sizeof(G));
-    G.one = table[0];
-    bool uploaded = false;
-    if (count > 1) {
-        PGraph *d_table = reinterpret_cast<PGraph *>(ws + pl.off_table);
-        uint32_t *d_seg = reinterpret_cast<uint32_t *>(ws + pl.off_seg);
-        if (hipMemcpyAsync(d_table, table.data(), table.size() * sizeof(PGraph), hipMemcpyHostToDevice, s) != hipSuccess ||
-            hipMemcpyAsync(d_seg, seg_graph.data(), seg_graph.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess)
-            return check_launch("pba: table upload");
-        G.table = d_table;
-        G.seg_graph = d_seg;
-        uploaded = true;
-    }
+    G.one = first;
     Factions fac{nullptr, nullptr, nullptr, nullptr};
     if (faction_off) {
         uint32_t *d_foff = reinterpret_cast<uint32_t *>(ws + pl.off_foff);
@@ -759,70 +910,10 @@ int pba_run_batch(const PbaGraphSpec *gs, uint32_t count, const uint32_t *factio
             (!umem.empty() && hipMemcpyAsync(d_umem, umem.data(), umem.size() * 4, hipMemcpyHostToDevice, s) != hipSuccess))
             return check_launch("pba_generate: faction upload");
         fac = Factions{d_foff, d_fmem, d_uoff, d_umem};
-        uploaded = true;
+        // The host tables die at return: wait for their copies.
+        if (hipStreamSynchronize(s) != hipSuccess) return check_launch("pba_generate: faction upload");
     }
-    // The host tables die at return: wait for their copies.
-    if (uploaded && hipStreamSynchronize(s) != hipSuccess) return check_launch("pba: table upload");
-
-    const int cus = device_cu_count();
-    const int res_grid = cus * 8;
-    const uint32_t S = pl.S;
-
-    // Phase 1.
-    { ProfScope _ps("pba_tile_table", s); pba_bases1<<<(S + 1 + 255) / 256, 256, 0, s>>>(G, S, pl.E, base1); }
-    uint64_t max_slots = 0;
-    for (uint32_t g = 0; g < count; ++g)
-        max_slots = std::max<uint64_t>(max_slots, ((gs[g].n + gs[g].P - 1) / gs[g].P) * gs[g].m);
-    // Workgroups per segment: enough to fill the chip, and a dispatch's
-    // work-item count stays far below 2^32.
-    const uint64_t want = (max_slots + kDrawThreads - 1) / kDrawThreads;
-    const uint32_t chunks = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>(want, std::max<uint64_t>(1, (uint64_t)cus * 64 / S + 1)));
-    Draw1Args d1{G, base1, chunks, fac, lab};
-    { ProfScope _ps("pba_draw1", s); pba_draw1<<<S * chunks, kDrawThreads, 0, s>>>(d1); }
-    { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<kXcd, 1024, 0, s>>>(base1, S, pl.xstride, xpre, xtot, queues); }
-    { ProfScope _ps("pba_resolve", s); pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{lab, base1, xpre, xtot, queues, err, S, pl.xstride}); }
-
-    // Count exchange.
-    { ProfScope _ps("pba_count", s); pba_count<<<S * pl.T1max, 256, pl.Pmax * 4, s>>>(CountArgs{G, lab, base1, H, pl.T1max}); }
-    if (pl.grouped) {
-        const uint32_t P = gs[0].P;
-        const uint64_t R = (uint64_t)P * table[0].T1;
-        dim3 gsc((unsigned)pl.groups, (P + 255) / 256);
-        { ProfScope _ps("pba_scan", s); pba_scan_partial<<<gsc, 256, 0, s>>>(H, R, P, part); }
-        { ProfScope _ps("pba_scan", s); pba_scan_groups<<<(P + 255) / 256, 256, 0, s>>>(part, pl.groups, P, D, err); }
-        { ProfScope _ps("pba_scan", s); pba_scan_apply<<<gsc, 256, 0, s>>>(H, R, P, part); }
-    } else {
-        { ProfScope _ps("pba_scan", s); pba_scan_columns<<<(S + 255) / 256, 256, 0, s>>>(G, S, H, D, err); }
-    }
-    { ProfScope _ps("pba_scan", s); pba_list_bases<<<1, 1024, 0, s>>>(D, S, sbase); }
-
-    // Phase 2.
-    Draw2Args d2{G, S, pl.E, sbase, sel};
-    { ProfScope _ps("pba_draw2", s); pba_draw2<<<(unsigned)((pl.E + kDrawThreads * kDraw2Items - 1) / (kDrawThreads * kDraw2Items)), kDrawThreads, 0, s>>>(d2); }
-    { ProfScope _ps("pba_tile_table", s); pba_tile_table<<<kXcd, 1024, 0, s>>>(sbase, S, pl.xstride, xpre, xtot, queues + kXcd); }
-    { ProfScope _ps("pba_resolve", s); pba_resolve<<<res_grid, kResThreads, 0, s>>>(ResolveArgs{sel, sbase, xpre, xtot, queues + kXcd, err, S, pl.xstride}); }
-
-    // Substitution.
-    SubArgs sa{G, lab, base1, H, sbase, sel, src, dst, pl.T1max, pl.Pmax};
-    const bool match = pl.Pmax <= kMatchParts;
-    const size_t lds = (size_t)4 * pl.Pmax * 4 + (match ? (size_t)4 * pl.Pmax * 8 : 0);
-    const unsigned gsub = S * pl.T1max;
-    {
-        ProfScope _ps("pba_substitute", s);
-        if (id_bytes == 4) {
-            if (match)
-                pba_substitute<int32_t, true><<<gsub, kSubThreads, lds, s>>>(sa);
-            else
-                pba_substitute<int32_t, false><<<gsub, kSubThreads, lds, s>>>(sa);
-        } else {
-            if (match)
-                pba_substitute<int64_t, true><<<gsub, kSubThreads, lds, s>>>(sa);
-            else
-                pba_substitute<int64_t, false><<<gsub, kSubThreads, lds, s>>>(sa);
-        }
-    }
-    return check_launch(who);
+    return enqueue(pl, G, fac, 1, first.T1, first.P, id_bytes, src, dst, ws, s, who);
 }
 
 }  // namespace sfg

@@ -24,7 +24,17 @@ struct PbaGraphSpec {
 
 size_t pba_batch_workspace_bytes(const PbaGraphSpec *gs, uint32_t count);
 int pba_check_spec(const PbaGraphSpec &g, int id_bytes, const char *who);
+
+// One graph with optional faction tables (pba_generate).
 int pba_run_batch(const PbaGraphSpec *gs, uint32_t count, const uint32_t *faction_off, const uint32_t *faction_members,
                   int id_bytes, void *src, void *dst, void *workspace, size_t workspace_bytes, hipStream_t s);
+
+// A batch of graphs with default factions whose device tables (pba_tables_bytes
+// bytes, built on the host by pba_tables_fill) the caller has uploaded to
+// dev_tables; enqueues kernel launches only.  One graph needs no tables.
+size_t pba_tables_bytes(const PbaGraphSpec *gs, uint32_t count);
+void pba_tables_fill(const PbaGraphSpec *gs, uint32_t count, void *host);
+int pba_enqueue_batch(const PbaGraphSpec *gs, uint32_t count, int id_bytes, void *src, void *dst, void *workspace,
+                      size_t workspace_bytes, const void *dev_tables, hipStream_t s);
 
 }  // namespace sfg

@@ -53,48 +53,56 @@ __device__ __forceinline__ uint32_t graph_of_chunk(const StatGraph *G, uint32_t 
 
 // One workgroup per chunk: degree histogram (integer atomics) and the
 // exponent's partial sum and count in a fixed order.
-__global__ __launch_bounds__(kChunkThreads) void stats_chunks(const StatGraph *G, uint32_t count, const uint64_t *raw,
-                                                              uint64_t *hist, double *psum, uint64_t *pcnt) {
+// Workgroups walk the chunks (persistent: a grid smaller than the chunk count
+// takes chunks blockIdx.x, blockIdx.x + gridDim.x, ...): degree histogram
+// (integer atomics) and the exponent's partial sum and count of each chunk in
+// a fixed order, so the grid does not change any result.
+__global__ __launch_bounds__(kChunkThreads) void stats_chunks(const StatGraph *G, uint32_t count, uint64_t total,
+                                                              const uint64_t *raw, uint64_t *hist, double *psum,
+                                                              uint64_t *pcnt) {
     __shared__ uint32_t s_h[32];
     __shared__ double s_sum[kChunkThreads];
     __shared__ uint64_t s_cnt[kChunkThreads];
     __shared__ uint32_t s_g;
-    const uint64_t c = blockIdx.x;
-    if (threadIdx.x == 0) s_g = graph_of_chunk(G, count, c);
-    if (threadIdx.x < 32) s_h[threadIdx.x] = 0;
-    __syncthreads();
-    const StatGraph &g = G[s_g];
-    const uint64_t v0 = g.v0 + (c - g.chunk0) * kChunk;
-    const double denom = (double)g.dmin - 0.5;
-    double sum = 0.0;
-    uint64_t cnt = 0;
-    for (int j = 0; j < kPer; ++j) {
-        const uint64_t v = v0 + (uint64_t)threadIdx.x * kPer + j;
-        if (v < g.v1) {
-            const uint64_t d = raw[v + 1] - raw[v];
-            atomicAdd(&s_h[log2_bin(d)], 1u);
-            if (d >= g.dmin && d > 0) {
-                sum += log((double)d / denom);
-                ++cnt;
+    for (uint64_t c = blockIdx.x; c < total; c += gridDim.x) {
+        if (threadIdx.x == 0) s_g = graph_of_chunk(G, count, c);
+        if (threadIdx.x < 32) s_h[threadIdx.x] = 0;
+        __syncthreads();
+        const StatGraph &g = G[s_g];
+        const uint64_t v0 = g.v0 + (c - g.chunk0) * kChunk;
+        const double denom = (double)g.dmin - 0.5;
+        double sum = 0.0;
+        uint64_t cnt = 0;
+        for (int j = 0; j < kPer; ++j) {
+            const uint64_t v = v0 + (uint64_t)threadIdx.x * kPer + j;
+            if (v < g.v1) {
+                const uint64_t d = raw[v + 1] - raw[v];
+                atomicAdd(&s_h[log2_bin(d)], 1u);
+                if (d >= g.dmin && d > 0) {
+                    sum += log((double)d / denom);
+                    ++cnt;
+                }
             }
         }
-    }
-    s_sum[threadIdx.x] = sum;
-    s_cnt[threadIdx.x] = cnt;
-    __syncthreads();
-    for (int off = kChunkThreads / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) {
-            s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
-            s_cnt[threadIdx.x] += s_cnt[threadIdx.x + off];
-        }
+        s_sum[threadIdx.x] = sum;
+        s_cnt[threadIdx.x] = cnt;
         __syncthreads();
+        for (int off = kChunkThreads / 2; off > 0; off >>= 1) {
+            if (threadIdx.x < off) {
+                s_sum[threadIdx.x] += s_sum[threadIdx.x + off];
+                s_cnt[threadIdx.x] += s_cnt[threadIdx.x + off];
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            psum[c] = s_sum[0];
+            pcnt[c] = s_cnt[0];
+        }
+        if (threadIdx.x < 32 && s_h[threadIdx.x])
+            atomicAdd((unsigned long long *)&hist[(uint64_t)g.out * 32 + threadIdx.x],
+                      (unsigned long long)s_h[threadIdx.x]);
+        __syncthreads();  // s_g, s_h and the partial sums are reused by the next chunk
     }
-    if (threadIdx.x == 0) {
-        psum[c] = s_sum[0];
-        pcnt[c] = s_cnt[0];
-    }
-    if (threadIdx.x < 32 && s_h[threadIdx.x])
-        atomicAdd((unsigned long long *)&hist[(uint64_t)g.out * 32 + threadIdx.x], (unsigned long long)s_h[threadIdx.x]);
 }
 
 // One workgroup per graph: the exponent from its chunks' partials.
@@ -282,7 +290,7 @@ size_t stats_scratch_bytes(uint64_t nv, uint64_t total_chunks) {
 
 int stats_enqueue(const StatGraph *G_dev, uint32_t count, uint64_t total_chunks, uint64_t nv, const uint64_t *raw,
                   const uint64_t *rp, const void *col, int id_bytes, uint32_t samples, uint64_t seed, uint64_t *hist,
-                  double *gamma, int64_t *closed, void *scratch, hipStream_t s) {
+                  double *gamma, int64_t *closed, void *scratch, hipStream_t s, uint32_t grid) {
     char *p = static_cast<char *>(scratch);
     uint64_t *pre = reinterpret_cast<uint64_t *>(p);
     p += align256(std::max<uint64_t>(nv, 1) * 8);
@@ -297,7 +305,8 @@ int stats_enqueue(const StatGraph *G_dev, uint32_t count, uint64_t total_chunks,
     { ProfScope _ps("stats_chunks", s); stats_clear<<<(count * 32 + 255) / 256, 256, 0, s>>>(G_dev, count, hist, cl); }
     if (total_chunks > 0) {
         ProfScope _ps("stats_chunks", s);
-        stats_chunks<<<(unsigned)total_chunks, kChunkThreads, 0, s>>>(G_dev, count, raw, hist, psum, pcnt);
+        const uint64_t g = grid ? std::min<uint64_t>(grid, total_chunks) : total_chunks;
+        stats_chunks<<<(unsigned)g, kChunkThreads, 0, s>>>(G_dev, count, total_chunks, raw, hist, psum, pcnt);
     }
     { ProfScope _ps("stats_gamma", s); stats_gamma<<<count, 256, 0, s>>>(G_dev, psum, pcnt, gamma); }
     if (nv > 0) {

@@ -59,6 +59,7 @@ SIGNATURES = {
     "path_stats": (_i32, [_u64, _vp, _vp, _i32, _vp, _u32, _vp, _vp, _sz, _vp]),
     "ensemble_workspace_bytes": (_sz, [_vp, _u32, _u64]),
     "ensemble_generate": (_i32, [_vp, _u32, _u32, _u64, _u64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "ensemble_generate_tuned": (_i32, [_vp, _u32, _u32, _u64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "mlp_param_count": (_sz, [_vp]),
     "mlp_workspace_bytes": (_sz, [_vp, _u32]),
     "mlp_forward": (_i32, [_vp, _u32, _vp, _vp, _vp, _vp, _sz, _vp]),
@@ -82,6 +83,17 @@ class GraphDesc(C.Structure):
 
 
 GRAPH_PBA, GRAPH_KRON = 0, 1
+ENSEMBLE_GRAPH = 1
+
+
+class EnsembleTuning(C.Structure):
+    """sfg_ensemble_tuning of include/sfgen.h."""
+    _fields_ = [("max_batch_edges", C.c_uint64), ("grid_per_cu", C.c_uint32), ("kron_items", C.c_uint32),
+                ("flags", C.c_uint32)]
+
+
+def ensemble_tuning(max_batch_edges=1 << 28, grid_per_cu=8, kron_items=8, graph=True):
+    return EnsembleTuning(max_batch_edges, grid_per_cu, kron_items, ENSEMBLE_GRAPH if graph else 0)
 
 
 def load(path: str = LIB_PATH):
@@ -432,8 +444,11 @@ def ensemble_workspace_bytes(descs, max_batch_edges):
 
 
 def ensemble_generate(descs, *, num_samples=10_000, stat_seed=0, max_batch_edges=1 << 28, ws=None, out=None,
-                      stream=None):
-    """Batched ensemble: returns (hist [count,32], gamma [count], closed [count]) device tensors."""
+                      stream=None, tuning=None, check=False):
+    """Batched ensemble: returns (hist [count,32], gamma [count], closed [count]) device tensors.
+    tuning: an EnsembleTuning (ensemble_tuning(...)); None = the library's
+    default tuning with this max_batch_edges.  check: synchronise and raise
+    SfgenError(EDEVICE) if a kernel reported a device error."""
     _require_cuda()
     lib = load()
     count = len(descs)
@@ -442,10 +457,20 @@ def ensemble_generate(descs, *, num_samples=10_000, stat_seed=0, max_batch_edges
                torch.empty(count, dtype=torch.float64, device="cuda"),
                torch.empty(count, dtype=torch.int64, device="cuda"))
     hist, gamma, closed = out
+    budget = tuning.max_batch_edges if tuning is not None else max_batch_edges
     if ws is None:
-        ws = workspace(ensemble_workspace_bytes(descs, max_batch_edges))
-    _check(lib.ensemble_generate(C.cast(descs, _vp), count, num_samples, stat_seed, max_batch_edges, _ptr(hist),
-                                 _ptr(gamma), _ptr(closed), _ptr(ws), ws.numel(), _stream(stream)))
+        ws = workspace(ensemble_workspace_bytes(descs, budget))
+    if tuning is None:
+        _check(lib.ensemble_generate(C.cast(descs, _vp), count, num_samples, stat_seed, max_batch_edges, _ptr(hist),
+                                     _ptr(gamma), _ptr(closed), _ptr(ws), ws.numel(), _stream(stream)))
+    else:
+        _check(lib.ensemble_generate_tuned(C.cast(descs, _vp), count, num_samples, stat_seed, C.byref(tuning),
+                                           _ptr(hist), _ptr(gamma), _ptr(closed), _ptr(ws), ws.numel(),
+                                           _stream(stream)))
+    if check:
+        code = device_error(stream)
+        if code:
+            raise SfgenError(SFG_EDEVICE, f"ensemble_generate: device error word {code}")
     return hist, gamma, closed
 
 

@@ -61,8 +61,7 @@ def generate_dataset(rows, samples=10_000, stat_seed=0, max_batch_edges=1 << 28,
     """Statistics of every graph in `rows` via the batched ensemble."""
     descs = sfg.graph_descs(rows)
     hist, gamma, closed = sfg.ensemble_generate(descs, num_samples=samples, stat_seed=stat_seed,
-                                                max_batch_edges=max_batch_edges, ws=ws)
-    torch.cuda.synchronize()
+                                                max_batch_edges=max_batch_edges, ws=ws, check=True)
     return targets(rows, hist.cpu().numpy().astype(np.float64), gamma.cpu().numpy(), closed.cpu().numpy(), samples)
 
 
@@ -309,3 +308,100 @@ def fit_exponent(model, judge, target, tol, budget=40, seed=0, surrogate_share=0
         return True, c, "surrogate"
     ok2, c2 = search_generator_only(judge, target, tol, budget=budget - c, seed=seed)
     return ok2, c + c2, "generator"
+
+
+# ----------------------------------------------------------------------------- the ensemble-scale study
+def generate_dataset_chunked(rows, samples=10_000, stat_seed=0, chunk=4096, max_batch_edges=1 << 28):
+    """(Y, M) of every graph in `rows`, made by ensemble_generate over
+    consecutive chunks of `chunk` members (one workspace reused; the batch
+    sequence is enqueued directly, since every chunk is a new table)."""
+    import numpy as np
+    Ys, Ms = [], []
+    ws = None
+    tu = sfg.ensemble_tuning(max_batch_edges, 8, 8, graph=False)
+    for c0 in range(0, len(rows), chunk):
+        part = rows[c0:c0 + chunk]
+        descs = sfg.graph_descs(part)
+        need = sfg.ensemble_workspace_bytes(descs, max_batch_edges)
+        if ws is None or ws.numel() < need:
+            ws = None
+            torch.cuda.empty_cache()
+            ws = sfg.workspace(need)
+        hist, gamma, closed = sfg.ensemble_generate(descs, num_samples=samples, stat_seed=stat_seed, ws=ws,
+                                                    tuning=tu, check=True)
+        Y, M = targets(part, hist.cpu().numpy().astype(np.float64), gamma.cpu().numpy(), closed.cpu().numpy(),
+                       samples)
+        Ys.append(Y)
+        Ms.append(M)
+    del ws
+    torch.cuda.empty_cache()
+    return np.concatenate(Ys, 0), np.concatenate(Ms, 0)
+
+
+def ensemble_study(rows, *, targets_gamma=tuple(round(2.1 + 0.1 * i, 1) for i in range(10)), k=14, tol=0.05,
+                   budget=40, heldout=4096, epochs=60, lr=2e-3, samples=10_000, stat_seed=5, judge_seeds=(31,),
+                   model_seed=1, log=None):
+    """Train the surrogate on the statistics of the ensemble `rows` (the
+    generators' own output), then fit the 2x2 Kronecker initiator
+    [[a, 1-a], [b, 1-b]] at k levels to every target exponent twice: with
+    the surrogate-guided search and with the generator-only search, each
+    judged by the real generator.  A target is reported infeasible when
+    neither search reaches it within the budget; the surrogate's closest
+    prediction over its inversion starts is reported beside it.  Returns a
+    dict of the figures (generator calls and seconds per target, with and
+    without the surrogate)."""
+    import time
+
+    import numpy as np
+    t0 = time.perf_counter()
+    Y, M = generate_dataset_chunked(rows, samples=samples, stat_seed=stat_seed)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - t0
+    if log:
+        log(f"dataset: {len(rows)} graphs in {gen_s:.1f} s")
+    X = features(rows)
+    n_train = len(rows) - heldout
+    model = Surrogate(batch=4096, seed=model_seed)
+    t1 = time.perf_counter()
+    hist = model.fit(X[:n_train], Y[:n_train], M[:n_train], epochs=epochs, lr=lr)
+    torch.cuda.synchronize()
+    fit_s = time.perf_counter() - t1
+    pred = Surrogate.gamma_of(model.predict(X[n_train:]))
+    ok = M[n_train:, GAMMA_COL] > 0
+    y = Surrogate.gamma_of(Y[n_train:])[ok]
+    err = np.abs(pred[ok] - y)
+    if log:
+        log(f"fit: {epochs} epochs in {fit_s:.1f} s, loss {hist[0]:.4f} -> {hist[-1]:.4f}, "
+            f"held-out median |gamma error| {np.median(err):.4f}")
+    judge = Judge(k=k, seeds=judge_seeds, samples=2000)
+    per = []
+    for i, t in enumerate(targets_gamma):
+        _, gpred = invert(model, float(t), k, seed=1000 + i)
+        ta = time.perf_counter()
+        ok1, c1 = search_with_surrogate(model, judge, float(t), tol, budget=budget, seed=i)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        ok2, c2 = search_generator_only(judge, float(t), tol, budget=budget, seed=i)
+        torch.cuda.synchronize()
+        tc = time.perf_counter()
+        per.append({"target": float(t), "feasible": bool(ok1 or ok2),
+                    "predicted_closest": float(gpred[0]),
+                    "with_surrogate": {"reached": bool(ok1), "generator_calls": int(c1), "seconds": tb - ta},
+                    "generator_only": {"reached": bool(ok2), "generator_calls": int(c2), "seconds": tc - tb}})
+        if log:
+            log(f"target {t}: with surrogate {c1} calls ({'ok' if ok1 else 'missed'}), "
+                f"generator only {c2} ({'ok' if ok2 else 'missed'})")
+    feasible = [p for p in per if p["feasible"]]
+
+    def mean(key, field):
+        return float(np.mean([p[key][field] for p in feasible])) if feasible else None
+
+    return {"train_graphs": n_train, "heldout_graphs": heldout, "dataset_s": gen_s, "fit_s": fit_s,
+            "epochs": epochs, "loss_first": hist[0], "loss_last": hist[-1],
+            "heldout_median_gamma_error": float(np.median(err)), "family": f"2x2 [[a,1-a],[b,1-b]], k={k}",
+            "tolerance": tol, "budget": budget, "targets": per,
+            "infeasible": [p["target"] for p in per if not p["feasible"]],
+            "mean_calls_with_surrogate": mean("with_surrogate", "generator_calls"),
+            "mean_calls_generator_only": mean("generator_only", "generator_calls"),
+            "mean_seconds_with_surrogate": mean("with_surrogate", "seconds"),
+            "mean_seconds_generator_only": mean("generator_only", "seconds")}
