@@ -207,6 +207,12 @@ int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p_inter, con
  * not fit); ENOSPACE.  Ids outside [0, n) are not detected (the caller's
  * contract): the output is then unspecified, but no kernel writes or reads
  * outside the buffers on their account.
+ * The sort's passes wait on earlier workgroups of the same launch (decoupled
+ * look-back), which relies on the pass being the only such kernel on the
+ * GPU: calls that sort (edges_to_csr, edges_to_csr_noalloc,
+ * kron_generate_csr, graph_stats, kron_xor_random, ensemble_generate*) must
+ * not overlap in time on one device, e.g. on two streams.  Their waits are
+ * bounded: an overlap is reported through sfg_device_error, never a hang.
  * ---------------------------------------------------------------------- */
 size_t edges_to_csr_workspace_bytes(uint64_t n, uint64_t num_edges, int id_bytes, uint32_t flags);
 int edges_to_csr(uint64_t n, uint64_t num_edges, const void *src, const void *dst, int id_bytes, uint32_t flags,
