@@ -92,7 +92,12 @@ struct FastArgs {
     uint64_t *keys;
     int key_shift;
     uint64_t key_sym;  // offset of the reversed entries, or 0
+    uint32_t *keys32;  // 4-byte keys (packed ids only)
+    int pack_groups, pack_bits;
+    const uint16_t *pack_tab;  // [2^pack_bits], see ByteCount
 };
+
+constexpr int kPackTabMax = 4096;  // group values of a packing table
 
 constexpr int kCountRows = 8;    // byte-count rows a sampler workgroup keeps in LDS
 constexpr int kCountCopies = 4;  // interleaved copies of every counter
@@ -128,9 +133,12 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
     // same byte (frequent for skewed initiators) would otherwise serialise
     // their LDS atomics on one address.
     __shared__ uint32_t s_cnt[CNT ? kCountRows * 256 * kCountCopies : 1];
+    __shared__ uint8_t s_pack[CNT && POW2 ? kPackTabMax : 1];
     const uint32_t copy = threadIdx.x % kCountCopies;
     if (CNT)
         for (uint32_t i = threadIdx.x; i < kCountRows * 256 * kCountCopies; i += kBlock) s_cnt[i] = 0;
+    if (CNT && POW2 && a.pack_groups)
+        for (uint32_t i = threadIdx.x; i < (1u << a.pack_bits); i += kBlock) s_pack[i] = (uint8_t)a.pack_tab[i];
     if (kGuide) {
         for (uint32_t i = threadIdx.x; i < kGuideSize; i += kBlock) {
             const uint32_t lo = i << (32 - kGuideBits), hi = lo | ((1u << (32 - kGuideBits)) - 1u);
@@ -188,17 +196,29 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
         src[i] = (IdT)u;
         dst[i] = (IdT)v;
         if (CNT) {
+            // The sort works on packed ids when packing is on, else on the ids.
+            AccT ku = u, kv = v;
+            if (POW2 && a.pack_groups) {
+                const AccT gmask = ((AccT)1 << a.pack_bits) - 1;
+                ku = 0;
+                kv = 0;
+                for (int j = a.pack_groups - 1; j >= 0; --j) {
+                    ku = (ku << 8) | (AccT)s_pack[(uint32_t)((u >> (a.pack_bits * j)) & gmask)];
+                    kv = (kv << 8) | (AccT)s_pack[(uint32_t)((v >> (a.pack_bits * j)) & gmask)];
+                }
+                if (a.keys32) __builtin_nontemporal_store(((uint32_t)ku << a.key_shift) | (uint32_t)kv, &a.keys32[i]);
+            }
             if (a.keys) {
-                __builtin_nontemporal_store(((uint64_t)u << a.key_shift) | (uint64_t)v, &a.keys[i]);
+                __builtin_nontemporal_store(((uint64_t)ku << a.key_shift) | (uint64_t)kv, &a.keys[i]);
                 if (a.key_sym)
-                    __builtin_nontemporal_store(((uint64_t)v << a.key_shift) | (uint64_t)u, &a.keys[a.key_sym + i]);
+                    __builtin_nontemporal_store(((uint64_t)kv << a.key_shift) | (uint64_t)ku, &a.keys[a.key_sym + i]);
             }
 #pragma unroll
             for (int q = 0; q < (int)sizeof(AccT); ++q) {
                 if (q < a.dst_bytes)
-                    atomicAdd(&s_cnt[((a.dst_row + q) * 256 + (uint32_t)((v >> (8 * q)) & 255u)) * kCountCopies + copy], 1u);
+                    atomicAdd(&s_cnt[((a.dst_row + q) * 256 + (uint32_t)((kv >> (8 * q)) & 255u)) * kCountCopies + copy], 1u);
                 if (q < a.src_bytes)
-                    atomicAdd(&s_cnt[((a.src_row + q) * 256 + (uint32_t)((u >> (8 * q)) & 255u)) * kCountCopies + copy], 1u);
+                    atomicAdd(&s_cnt[((a.src_row + q) * 256 + (uint32_t)((ku >> (8 * q)) & 255u)) * kCountCopies + copy], 1u);
             }
         }
     }
@@ -464,7 +484,10 @@ bool count_ok(const ByteCount &bc, uint64_t count, int id_bytes) {
     if (bc.dst_row < 0 || bc.src_row < 0 || bc.dst_row + bc.dst_bytes > kCountRows ||
         bc.src_row + bc.src_bytes > kCountRows)
         return false;
-    if (bc.keys && (bc.key_shift < 1 || bc.key_shift > 32)) return false;
+    if ((bc.keys || bc.keys32) && (bc.key_shift < 1 || bc.key_shift > 32)) return false;
+    if (bc.pack_groups && (bc.pack_groups < 1 || bc.pack_bits < 1 || bc.pack_bits > 12 || !bc.pack_tab || bc.key_sym ||
+                           (1 << bc.pack_bits) > kPackTabMax))
+        return false;
     const uint64_t threads = (uint64_t)grid_for(count) * kBlock;
     const uint64_t per_group = (count + threads - 1) / threads * kBlock;
     return 2 * per_group < (1ull << 32);
@@ -580,7 +603,7 @@ int kron_generate_counted(uint32_t n0, const float *initiator, uint32_t k, uint6
             a.lut_row |= (uint64_t)tab.row[b] << (4 * b);
             a.lut_col |= (uint64_t)tab.col[b] << (4 * b);
         }
-        const bool cnt = bc && count_ok(*bc, count, id_bytes);
+        const bool cnt = bc && count_ok(*bc, count, id_bytes) && (pow2 || !bc->pack_groups);
         if (cnt) {
             a.hist = bc->hist;
             a.rows = bc->rows;
@@ -592,6 +615,12 @@ int kron_generate_counted(uint32_t n0, const float *initiator, uint32_t k, uint6
             a.keys = bc->keys;
             a.key_shift = bc->key_shift;
             a.key_sym = bc->key_sym ? count : 0;
+            if (pow2) {
+                a.keys32 = bc->keys32;
+                a.pack_groups = bc->pack_groups;
+                a.pack_bits = bc->pack_bits;
+                a.pack_tab = bc->pack_tab;
+            }
         }
         if (id_bytes == 4)
             launch_fast_any<int32_t, uint32_t>(a, pow2, cnt, tab.nt, src, dst, s);

@@ -30,6 +30,18 @@ int build_sample_table(uint32_t n0, const float *W, SampleTable &tab);
 // e: keys[e] = (src << key_shift) | dst, and with key_sym also
 // keys[num_edges + e] = (dst << key_shift) | src (the reversed entry of a
 // symmetrized CSR).
+//
+// Packed ids (pack_groups > 0, power-of-two n0, no key_sym): when the ids'
+// base-n0 digits only take the values 0 .. r-1 (an initiator whose last rows
+// and columns are zero), every group of g digits (pack_bits = g log2(n0)
+// bits of the id, least significant group first) is replaced by its base-r
+// value, one byte per group (r^g <= 255): pack(id) = sum_j
+// pack_tab[group_j(id)] << 8 j.  pack is increasing, so keys of packed ids
+// sort exactly like keys of the ids.  The counted bytes and the keys are
+// then those of the packed ids (the written src / dst stay the ids); 4-byte
+// keys go to keys32.  pack_tab (device, 2^pack_bits entries) holds for every
+// group value the base-r value of the smallest digit-valid group >= it (low
+// byte), plus 256 when the group itself is digit-valid.
 struct ByteCount {
     uint64_t *hist;
     int rows, row_mod;
@@ -37,6 +49,9 @@ struct ByteCount {
     uint64_t *keys;
     int key_shift;
     bool key_sym;
+    uint32_t *keys32;
+    int pack_groups, pack_bits;
+    const uint16_t *pack_tab;
 };
 
 // kron_generate_range with an optional ByteCount.  *counted tells whether the

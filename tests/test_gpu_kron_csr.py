@@ -115,3 +115,34 @@ def test_kron_csr_errors(sfg):
     with pytest.raises(sfg.SfgenError):
         sfg.kron_generate_csr(2, np.ones((2, 2)), 4, 10, graph_id=1 << 24)
     torch.cuda.synchronize()
+
+
+def _padded(n0, used, rng):
+    """An n0 x n0 initiator whose rows and columns from `used` on are zero, so
+    every digit of an id stays below `used` (ids are packed for the sort)."""
+    W = np.zeros((n0, n0), np.float32)
+    W[:used, :used] = rng.uniform(0.05, 1.0, size=(used, used))
+    return W
+
+
+@pytest.mark.parametrize("n0,used,ks", [(4, 3, (1, 4, 5, 6, 9, 11, 12)), (4, 2, (3, 9)), (8, 5, (2, 5, 7))])
+def test_kron_csr_packed_ids(sfg, orc, n0, used, ks):
+    """Zero-padded initiators (the 1B-vertex workload's 3x3 inside 4x4 among
+    them): the directed CSR with degree histogram is sorted on packed ids
+    (`used`-ary digits, several per byte), its columns unpacked by the last
+    pass and its row starts expanded to all n0^k ids; outputs equal the
+    oracle's for both id widths, ragged edge counts, and level counts that
+    leave a partial top group."""
+    rng = np.random.default_rng(600 + n0 * 10 + used)
+    for k in ks:
+        W = _padded(n0, used, rng)
+        E = int(rng.integers(1, 400_000))
+        for ib in (4, 8):
+            c = dict(n0=n0, initiator=W, k=k, num_edges=E, seed=int(rng.integers(0, 2 ** 62)),
+                     graph_id=int(rng.integers(0, 1 << 24)), id_bytes=ib)
+            _check(sfg, orc, c, 0, want_hist=True)
+    # the other flag sets and no histogram take the unpacked path on the same inputs
+    W = _padded(n0, used, rng)
+    c = dict(n0=n0, initiator=W, k=ks[-1], num_edges=100_003, seed=5, id_bytes=4)
+    for flags, want_hist in ((0, False), (1, True), (3, True)):
+        _check(sfg, orc, c, flags, want_hist=want_hist)
