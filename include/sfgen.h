@@ -85,7 +85,7 @@ int sfg_device_error(void *stream, uint32_t *code);
  * "pba_substitute", "stats_chunks", "stats_gamma",
  * "stats_wedge_scan", "stats_wedge", "path_level", "block_count",
  * "random_pairs", "perturb_expand", "mlp_gemm", "mlp_elementwise",
- * "mlp_adam". */
+ * "mlp_adam", "mlp_round", "mlp_rows", "mlp_wgrad", "mlp_update". */
 int sfg_profile_enable(int on);
 int sfg_profile_reset(void);
 int sfg_profile_query(const char *name, uint64_t *launches, double *total_ms);
@@ -528,6 +528,32 @@ int adam_step(uint64_t count, float *params, const float *grad, float *m, float 
  * device powf, so results may differ in the last bit from adam_step. */
 int adam_step_device(uint64_t count, float *params, const float *grad, float *m, float *v, const float *lr,
                      float beta1, float beta2, float eps, uint32_t *step, void *stream);
+
+/* One whole training step in four kernel launches: the forward pass, the
+ * weighted squared-error loss and its gradient, the backward pass and Adam
+ * (with the learning rate and the step counter in device memory, as
+ * adam_step_device), with the rounding points above.  The first launch
+ * rounds the weights to bfloat16 (row-major and transposed); the second
+ * runs, for every block of 64 rows, the forward pass, the loss gradient and
+ * the chain of activation gradients on the matrix cores with the layer
+ * operand in LDS; the third computes every weight-gradient tile over each
+ * 256-row slice of the batch on the matrix cores; the fourth sums the
+ * slices and the per-block bias sums in a fixed order and applies Adam.
+ * Results equal mlp_forward, mlp_mse_grad, mlp_backward and adam_step_device
+ * up to the float32 summation order.
+ * x, target, mask: device [rows of the data][d_in or d_out]; row r of the
+ *   batch is row rows[r] of them (rows: device int64 [batch], or NULL for
+ *   row r), so a shuffled batch needs no gather; mask and col_weight
+ *   nullable (ones).
+ * loss:  device float, the batch's loss (as mlp_mse_grad).
+ * grad:  device [param count] or NULL: a copy of the gradient.
+ * Layers at most 256 wide and at most 8 linear layers (EINVAL otherwise).
+ * workspace: device, mlp_train_workspace_bytes(shape, batch). */
+size_t mlp_train_workspace_bytes(const sfg_mlp_shape *shape, uint32_t batch);
+int mlp_train_step(const sfg_mlp_shape *shape, uint32_t batch, float *params, const float *x, const float *target,
+                   const float *mask, const float *col_weight, const int64_t *rows, float *m, float *v,
+                   const float *lr, float beta1, float beta2, float eps, uint32_t *step, float *loss, float *grad,
+                   void *workspace, size_t workspace_bytes, void *stream);
 
 #ifdef __cplusplus
 }

@@ -277,6 +277,423 @@ __global__ void adam_kernel_dev(uint64_t n, float *p, const float *g, float *m, 
     }
 }
 
+
+// ----------------------------------------------------------------------------- fused training step
+// One training step in four launches.  mlp_round writes the bf16 weights,
+// row-major and transposed.  mlp_rows runs, for a block of 64 rows, the
+// forward pass, the loss gradient and the whole backward chain of activation
+// gradients -- all of it row-local -- on the matrix cores, keeping the
+// current layer's bf16 operand in LDS; it leaves the bf16 layer inputs, the
+// bf16 gradients dZb and per-block column sums of dZ.  mlp_wgrad computes
+// every weight-gradient tile over a 256-row slice of the batch (dW = dZb^T
+// Xb) into per-slice partials; mlp_update sums the partials and the
+// per-block bias sums in a fixed order, applies Adam and sums the loss.  The
+// rounding points are those of mlp_forward / mlp_backward.
+//
+// The saved activations are feature-major, [feature][Bp], with the feature
+// count padded to a multiple of 16 and the batch to Bp, a multiple of 64:
+// a lane's four consecutive rows of one feature (the matrix-core output
+// layout) are one vector store, the weight-gradient operands (contiguous in
+// the batch) are direct fragment loads, and every element of the padding is
+// written by every step -- zero in Xb and dZb for rows beyond the batch and
+// features beyond the layer, so that they add exact zeros to dW.
+constexpr int kFR = 64;       // rows per block of mlp_rows
+constexpr int kFMax = 256;    // widest layer the fused step takes
+constexpr int kFMaxL = 8;     // deepest network the fused step takes
+constexpr int kWSlice = 256;  // batch rows per weight-gradient partial
+constexpr int kRW = 8;        // waves per block of mlp_rows
+constexpr int kCT = 2;        // column tiles per wave of mlp_rows
+
+struct TrainArgs {
+    int L, B, Bp;          // Bp: the batch rounded up to kFR
+    int dims[kFMaxL + 1];  // dims[0] = d_in, dims[l + 1] = outputs of layer l
+    size_t w_off[kFMaxL], b_off[kFMaxL];
+    float *params;
+    const bf16 *wb, *wbt;  // bf16 weights, per layer [out][in] and [in][out], at w_off
+    const float *x, *target, *mask, *cw;
+    const int64_t *rows;  // batch row r is row rows[r] of x, target and mask (null: row r)
+    bf16 *xb[kFMaxL];     // [pad16(dims[l])][Bp] layer inputs
+    float *z[kFMaxL];     // [pad16(dims[l + 1])][Bp] pre-activations (hidden layers)
+    bf16 *dzb[kFMaxL];    // [pad16(dims[l + 1])][Bp]
+    float *dbp[kFMaxL];   // [blocks][dims[l + 1]] column sums of dZ per block
+    float *lossp;         // [blocks]
+    uint32_t *step;       // advanced by block 0 of mlp_rows
+};
+
+__host__ __device__ __forceinline__ int round16(int x) { return (x + 15) & ~15; }
+__device__ __forceinline__ int round32(int x) { return (x + 31) & ~31; }
+
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+
+// bf16 weights: wb[w_off + n * in + k] = bf16(W[n][k]), wbt[w_off + k * out + n] = the same.
+__global__ void mlp_round(TrainArgs a) {
+    for (int l = 0; l < a.L; ++l) {
+        const int in = a.dims[l], out = a.dims[l + 1], n = in * out;
+        const float *W = a.params + a.w_off[l];
+        bf16 *wb = const_cast<bf16 *>(a.wb) + a.w_off[l], *wbt = const_cast<bf16 *>(a.wbt) + a.w_off[l];
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+            const bf16 v = f2bf(W[i]);
+            wb[i] = v;
+            wbt[(i % in) * out + i / in] = v;
+        }
+    }
+}
+
+// 8 consecutive bf16 of row n of a [rows][ld] matrix from column k (k a
+// multiple of 8); zero outside [0, rows) x [0, cols).  vec: M is 16-byte
+// aligned and ld a multiple of 8.
+__device__ __forceinline__ bf16x8 frag(const bf16 *M, int ld, int rows, int cols, int n, int k, bool vec) {
+    if (vec && n < rows && k + 8 <= cols) return *reinterpret_cast<const bf16x8 *>(M + (size_t)n * ld + k);
+    bf16x8 f;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) f[e] = (n < rows && k + e < cols) ? M[(size_t)n * ld + k + e] : f2bf(0.f);
+    return f;
+}
+
+// C (64 rows x N) = A (64 x K, bf16 in LDS, row stride kFMax + 8) * M^T with
+// M (N x K) bf16 row-major (ld = Kreal).  Wave w of the kRW waves takes the
+// column tiles w and w + kRW (N <= 256).  All of the wave's M fragments for
+// the layer (K <= 256: at most 8 k-steps) are loaded before the first
+// product, so a layer costs one round trip to L2 instead of one per k-step.
+__device__ __forceinline__ void rows_gemm(const bf16 (*sA)[kFMax + 8], int K, const bf16 *M, int N, int Kreal,
+                                          floatx4 (&acc)[4][kCT]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane % 16, kq = 8 * (lane / 16);
+    const int ntiles = (N + 15) / 16;
+    const bool vec = ((uintptr_t)M % 16) == 0 && Kreal % 8 == 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < kCT; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    bf16x8 fb[kFMax / kKStep][kCT];
+#pragma unroll
+    for (int st = 0; st < kFMax / kKStep; ++st)
+#pragma unroll
+        for (int j = 0; j < kCT; ++j) {
+            const int ct = w + kRW * j;
+            if (st * kKStep < K && ct < ntiles) fb[st][j] = frag(M, Kreal, N, Kreal, 16 * ct + r, st * kKStep + kq, vec);
+        }
+#pragma unroll
+    for (int st = 0; st < kFMax / kKStep; ++st) {
+        if (st * kKStep >= K) break;
+        bf16x8 fa[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) fa[i] = *reinterpret_cast<const bf16x8 *>(&sA[16 * i + r][st * kKStep + kq]);
+#pragma unroll
+        for (int j = 0; j < kCT; ++j)
+            if (w + kRW * j < ntiles)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[st][j], acc[i][j], 0, 0, 0);
+    }
+}
+
+// Column sums over the block's 64 rows of v (a lane's 4 x 4 values per
+// column tile), in a fixed order, written to out[c].
+__device__ __forceinline__ void block_col_sums(const float (&v)[4][kCT][4], int N, float *out) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ntiles = (N + 15) / 16;
+#pragma unroll
+    for (int j = 0; j < kCT; ++j) {
+        const int ct = w + kRW * j;
+        float s = 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s += v[i][j][e];
+        s += __shfl_xor(s, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        const int c = 16 * ct + lane % 16;
+        if (ct < ntiles && lane < 16 && c < N) out[c] = s;
+    }
+}
+
+// Lane layout of the 64 x 16 output tile (i, column tile ct) of rows_gemm:
+// column c = 16 ct + lane % 16, rows 16 i + 4 (lane / 16) + e, e = 0..3.
+// Each epilogue issues its global loads before any of its global stores (a
+// load issued after a store waits for that store's completion too), and
+// branches only on wave-uniform tile indices.
+__global__ __launch_bounds__(64 * kRW) void mlp_rows(TrainArgs a) {
+    __shared__ __align__(16) bf16 sA[kFR][kFMax + 8];
+    __shared__ int64_t s_src[kFR];  // data row of each batch row (-1 beyond the batch)
+    __shared__ float s_loss[kRW];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int r0 = blockIdx.x * kFR, Bp = a.Bp;
+    const int L = a.L;
+    const int rq = 4 * (lane / 16), cl = lane % 16;
+    const bf16 bz = f2bf(0.f);
+    if (blockIdx.x == 0 && tid == 0) *a.step += 1;
+    if (tid < kFR) s_src[tid] = r0 + tid < a.B ? (a.rows ? a.rows[r0 + tid] : (int64_t)(r0 + tid)) : -1;
+    __syncthreads();
+    // Xb_0 = bf16(x), zero beyond d_in (up to the padded K) and beyond the batch.
+    {
+        const int din = a.dims[0], K = round32(din), n = kFR * K, P = round16(din);
+        for (int i0 = 0; i0 < n; i0 += 64 * kRW * 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + 64 * kRW * u + tid, c = i / kFR, r = i % kFR;
+                v[u] = (i < n && c < din && s_src[r] >= 0) ? a.x[(size_t)s_src[r] * din + c] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int i = i0 + 64 * kRW * u + tid, c = i / kFR, r = i % kFR;
+                if (i >= n) continue;
+                const bf16 xb = f2bf(v[u]);
+                sA[r][c] = xb;
+                if (c < P) a.xb[0][(size_t)c * Bp + r0 + r] = xb;
+            }
+        }
+    }
+    __syncthreads();
+    floatx4 acc[4][kCT];
+    float keep[4][kCT][4];  // fp32 dZ of this lane's outputs (loss / activation gradients)
+    float lsum = 0.f;
+    // ---------------- forward: Z = Xb Wb^T + b
+    for (int l = 0; l < L; ++l) {
+        const int in = a.dims[l], out = a.dims[l + 1];
+        const bool last = l == L - 1;
+        const int npad = round32(out), ntiles = (out + 15) / 16;
+        float bj[kCT], cwj[kCT];
+#pragma unroll
+        for (int j = 0; j < kCT; ++j) {
+            const int c = 16 * (w + kRW * j) + cl;
+            bj[j] = c < out ? a.params[a.b_off[l] + c] : 0.f;
+            cwj[j] = (last && c < out && a.cw) ? a.cw[c] : 1.f;
+        }
+        rows_gemm(sA, round32(in), a.wb + a.w_off[l], out, in, acc);
+        __syncthreads();  // every wave is done reading sA
+        if (!last) {
+#pragma unroll
+            for (int j = 0; j < kCT; ++j) {
+                const int ct = w + kRW * j, c = 16 * ct + cl;
+                if (16 * ct >= npad) continue;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    floatx4 zv;
+                    bf16x4 xv;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = 16 * i + rq + e;
+                        const float z = acc[i][j][e] + bj[j];
+                        const bf16 xn = (c < out && r0 + r < a.B) ? f2bf(z * sigmoidf_(z)) : bz;
+                        sA[r][c] = xn;
+                        zv[e] = z;
+                        xv[e] = xn;
+                    }
+                    if (ct < ntiles) {
+                        const size_t gi = (size_t)c * Bp + r0 + 16 * i + rq;
+                        *reinterpret_cast<floatx4 *>(a.z[l] + gi) = zv;
+                        *reinterpret_cast<bf16x4 *>(a.xb[l + 1] + gi) = xv;
+                    }
+                }
+            }
+        } else {
+            // loss gradient dy = 2 w_c m (y - t) / B and the rows' loss terms;
+            // the targets and mask entries of a column tile, then its stores.
+#pragma unroll
+            for (int j = 0; j < kCT; ++j) {
+                const int ct = w + kRW * j, c = 16 * ct + cl;
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) keep[i][j][e] = 0.f;
+                if (16 * ct >= npad) continue;
+                float tg[4][4], mk[4][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int64_t src = s_src[16 * i + rq + e];
+                        const bool ok = c < out && src >= 0;
+                        const size_t si = ok ? (size_t)src * out + c : 0;
+                        tg[i][e] = a.target[si];
+                        mk[i][e] = a.mask ? a.mask[si] : 1.f;
+                    }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    bf16x4 gv;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int r = 16 * i + rq + e;
+                        const bool ok = c < out && r0 + r < a.B;
+                        const float wgt = cwj[j] * mk[i][e];
+                        const float d = (acc[i][j][e] + bj[j]) - tg[i][e];
+                        const float dy = (ok && wgt != 0.f) ? 2.f * wgt * d / (float)a.B : 0.f;
+                        lsum += (ok && wgt != 0.f) ? wgt * d * d : 0.f;
+                        keep[i][j][e] = dy;
+                        const bf16 g = f2bf(dy);
+                        sA[r][c] = g;
+                        gv[e] = g;
+                    }
+                    if (ct < ntiles)
+                        *reinterpret_cast<bf16x4 *>(a.dzb[l] + (size_t)c * Bp + r0 + 16 * i + rq) = gv;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // the loss of the block's rows (fixed order: lanes, then waves)
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (lane == 0) s_loss[w] = lsum;
+    // ---------------- backward: dZ_{l-1} = (dZb_l Wb_l) * SiLU'(Z_{l-1})
+    block_col_sums(keep, a.dims[L], a.dbp[L - 1] + (size_t)blockIdx.x * a.dims[L]);
+    for (int l = L - 1; l >= 1; --l) {
+        const int out = a.dims[l + 1], in = a.dims[l];
+        const int npad = round32(in), ntiles = (in + 15) / 16;
+        // dH (64 x in) = dZb (64 x out) Wb (out x in): M = Wb^T, [in][out]
+        rows_gemm(sA, round32(out), a.wbt + a.w_off[l], in, out, acc);
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kCT; ++j) {
+            const int ct = w + kRW * j, c = 16 * ct + cl;
+            floatx4 zv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                zv[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+                if (ct < ntiles) zv[i] = *reinterpret_cast<const floatx4 *>(a.z[l - 1] + (size_t)c * Bp + r0 + 16 * i + rq);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                bf16x4 gv;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int r = 16 * i + rq + e;
+                    const float zz = zv[i][e], s = sigmoidf_(zz);
+                    const float g = (c < in && r0 + r < a.B) ? acc[i][j][e] * (s * (1.0f + zz * (1.0f - s))) : 0.f;
+                    keep[i][j][e] = g;
+                    const bf16 gb = f2bf(g);
+                    if (16 * ct < npad) sA[r][c] = gb;
+                    gv[e] = gb;
+                }
+                if (ct < ntiles) *reinterpret_cast<bf16x4 *>(a.dzb[l - 1] + (size_t)c * Bp + r0 + 16 * i + rq) = gv;
+            }
+        }
+        block_col_sums(keep, in, a.dbp[l - 1] + (size_t)blockIdx.x * in);
+        __syncthreads();
+    }
+    if (tid == 0) {
+        float t = 0.f;
+        for (int q = 0; q < kRW; ++q) t += s_loss[q];
+        a.lossp[blockIdx.x] = t;
+    }
+}
+
+// Weight-gradient tile (64 x 64) of one layer over one slice of up to 256
+// batch rows: part[slice][w_off + j * in + i] = sum over the slice's rows r
+// of dZb[j][r] Xb[i][r] (both feature-major: the matrix-core fragments are
+// 16-byte loads, all of a slice's issued before the first product).
+// Workgroup b: tile b / slices (layers in order, each row-major in 64 x 64
+// tiles), slice b % slices.
+struct WgradArgs {
+    TrainArgs t;
+    int slices;
+    size_t nparams;
+    float *part;  // [slices][nparams]
+};
+
+__global__ __launch_bounds__(256) void mlp_wgrad(WgradArgs a) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int slice = (int)blockIdx.x % a.slices;
+    int l = 0, rem = (int)blockIdx.x / a.slices;
+    for (; l < a.t.L; ++l) {
+        const int mt = (a.t.dims[l + 1] + kTile - 1) / kTile, nt = (a.t.dims[l] + kTile - 1) / kTile;
+        if (rem < mt * nt) break;
+        rem -= mt * nt;
+    }
+    const int out = a.t.dims[l + 1], in = a.t.dims[l], Bp = a.t.Bp;
+    const int ntl = (in + kTile - 1) / kTile;
+    const int m0 = (rem / ntl) * kTile, n0 = (rem % ntl) * kTile;
+    const int kb = slice * kWSlice, steps = (std::min(Bp, kb + kWSlice) - kb) / kKStep;
+    const int r = lane % 16, kq = 8 * (lane / 16);
+    const int mp = round16(out), np = round16(in);
+    const bf16 *A = a.t.dzb[l], *Bm = a.t.xb[l];
+    bf16x8 fa[kWSlice / kKStep][2], fb[kWSlice / kKStep][2];
+#pragma unroll
+    for (int st = 0; st < kWSlice / kKStep; ++st)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int gm = m0 + 32 * (w / 2) + 16 * i + r, gn = n0 + 32 * (w % 2) + 16 * i + r;
+            const size_t k = (size_t)kb + st * kKStep + kq;
+            fa[st][i] = bf16x8{};
+            fb[st][i] = bf16x8{};
+            if (st < steps && gm < mp) fa[st][i] = *reinterpret_cast<const bf16x8 *>(A + (size_t)gm * Bp + k);
+            if (st < steps && gn < np) fb[st][i] = *reinterpret_cast<const bf16x8 *>(Bm + (size_t)gn * Bp + k);
+        }
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int st = 0; st < kWSlice / kKStep; ++st)
+        if (st < steps)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[st][i], fb[st][j], acc[i][j], 0, 0, 0);
+    float *P = a.part + (size_t)slice * a.nparams + a.t.w_off[l];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int gm = m0 + 32 * (w / 2) + 16 * i + 4 * (lane / 16) + e;
+                const int gn = n0 + 32 * (w % 2) + 16 * j + lane % 16;
+                if (gm < out && gn < in) P[(size_t)gm * in + gn] = acc[i][j][e];
+            }
+}
+
+// Every parameter: its gradient (weight: the slice partials in slice order;
+// bias: the per-block sums in block order), Adam, and the loss.
+struct UpdateArgs {
+    TrainArgs t;
+    int slices, blocks;
+    size_t nparams;
+    const float *part;
+    float *m, *v, *grad;
+    const float *lr;
+    float b1, b2, eps;
+    float *loss;
+};
+
+// Sum of v[0], v[stride], ..., v[(n - 1) stride] in index order, 16 loads in
+// flight at a time.
+__device__ __forceinline__ float ordered_sum(const float *v, int n, size_t stride) {
+    float g = 0.f;
+    for (int z0 = 0; z0 < n; z0 += 16) {
+        float t[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) t[u] = z0 + u < n ? v[(size_t)(z0 + u) * stride] : 0.f;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (z0 + u < n) g += t[u];
+    }
+    return g;
+}
+
+__global__ void mlp_update(UpdateArgs a) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.loss = ordered_sum(a.t.lossp, a.blocks, 1) / (float)a.t.B;
+    const float t = (float)*a.t.step, lr = *a.lr;
+    const float c1 = 1.f - powf(a.b1, t), c2 = 1.f - powf(a.b2, t);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.nparams;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        int l = 0;
+        while (l + 1 < a.t.L && i >= a.t.w_off[l + 1]) ++l;
+        const float g = i < a.t.b_off[l]
+                            ? ordered_sum(a.part + i, a.slices, a.nparams)
+                            : ordered_sum(a.t.dbp[l] + (i - a.t.b_off[l]), a.blocks, (size_t)a.t.dims[l + 1]);
+        const float mi = a.b1 * a.m[i] + (1.f - a.b1) * g;
+        const float vi = a.b2 * a.v[i] + (1.f - a.b2) * g * g;
+        a.m[i] = mi;
+        a.v[i] = vi;
+        a.t.params[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + a.eps);
+        if (a.grad) a.grad[i] = g;
+    }
+}
+
 // ----------------------------------------------------------------------------- host
 struct Layer {
     int in, out;
@@ -286,7 +703,7 @@ struct Layer {
 struct Net {
     int L = 0;  // linear layers
     Layer layer[16];
-    size_t nparams = 0, nweights = 0;
+    size_t nparams = 0;
     int maxw = 0;
 };
 
@@ -461,4 +878,108 @@ extern "C" int adam_step_device(uint64_t count, float *params, const float *grad
     adam_tick<<<1, 1, 0, s>>>(step);
     adam_kernel_dev<<<grid_n(count), 256, 0, s>>>(count, params, grad, m, v, lr, beta1, beta2, eps, step);
     return check_launch("adam_step_device");
+}
+
+// ----------------------------------------------------------------------------- fused training step (host)
+namespace sfg {
+namespace {
+
+struct TrainWs {
+    TrainArgs t;
+    int blocks, slices;
+    float *part;
+    size_t total;
+};
+
+bool fused_ok(const Net &net) {
+    if (net.L > kFMaxL) return false;
+    for (int l = 0; l < net.L; ++l)
+        if (net.layer[l].in > kFMax || net.layer[l].out > kFMax) return false;
+    return true;
+}
+
+TrainWs carve_train(const Net &net, uint32_t B, void *base) {
+    TrainWs w;
+    memset(&w, 0, sizeof(w));
+    Carver c(base);
+    w.blocks = (int)((B + kFR - 1) / kFR);
+    const int Bp = w.blocks * kFR;
+    w.slices = (Bp + kWSlice - 1) / kWSlice;
+    w.t.L = net.L;
+    w.t.B = (int)B;
+    w.t.Bp = Bp;
+    w.t.dims[0] = net.layer[0].in;
+    w.t.wb = c.take<bf16>(net.nparams);
+    w.t.wbt = c.take<bf16>(net.nparams);
+    for (int l = 0; l < net.L; ++l) {
+        const size_t pin = round16(net.layer[l].in), pout = round16(net.layer[l].out);
+        w.t.dims[l + 1] = net.layer[l].out;
+        w.t.w_off[l] = net.layer[l].w_off;
+        w.t.b_off[l] = net.layer[l].b_off;
+        w.t.xb[l] = c.take<bf16>(pin * Bp);
+        w.t.z[l] = l + 1 < net.L ? c.take<float>(pout * Bp) : nullptr;
+        w.t.dzb[l] = c.take<bf16>(pout * Bp);
+        w.t.dbp[l] = c.take<float>((size_t)w.blocks * net.layer[l].out);
+    }
+    w.t.lossp = c.take<float>(w.blocks);
+    w.part = c.take<float>((size_t)w.slices * net.nparams);
+    w.total = c.used;
+    return w;
+}
+
+}  // namespace
+}  // namespace sfg
+
+extern "C" size_t mlp_train_workspace_bytes(const sfg_mlp_shape *shape, uint32_t batch) {
+    Net net;
+    if (!make_net(shape, net) || !fused_ok(net) || batch == 0) return 0;
+    return carve_train(net, batch, nullptr).total;
+}
+
+extern "C" int mlp_train_step(const sfg_mlp_shape *shape, uint32_t batch, float *params, const float *x,
+                              const float *target, const float *mask, const float *col_weight, const int64_t *rows,
+                              float *m, float *v,
+                              const float *lr, float beta1, float beta2, float eps, uint32_t *step, float *loss,
+                              float *grad, void *workspace, size_t workspace_bytes, void *stream) {
+    Net net;
+    if (!make_net(shape, net)) return fail(SFG_EINVAL, "mlp_train_step: bad shape");
+    if (!fused_ok(net)) return fail(SFG_EINVAL, "mlp_train_step: layers wider than 256 or more than 8 layers");
+    if (batch == 0 || batch > (1u << 24)) return fail(SFG_EINVAL, "mlp_train_step: batch must be in [1, 2^24]");
+    if (!params || !x || !target || !m || !v || !lr || !step || !loss || !workspace)
+        return fail(SFG_EINVAL, "mlp_train_step: NULL buffer");
+    TrainWs w = carve_train(net, batch, workspace);
+    if (workspace_bytes < w.total)
+        return fail(SFG_ENOSPACE, "mlp_train_step: workspace too small (%zu < %zu)", workspace_bytes, w.total);
+    w.t.params = params;
+    w.t.x = x;
+    w.t.target = target;
+    w.t.mask = mask;
+    w.t.cw = col_weight;
+    w.t.rows = rows;
+    w.t.step = step;
+    hipStream_t s = as_stream(stream);
+    int ntiles = 0;
+    for (int l = 0; l < net.L; ++l)
+        ntiles += ((net.layer[l].out + kTile - 1) / kTile) * ((net.layer[l].in + kTile - 1) / kTile);
+    { ProfScope _ps("mlp_round", s); mlp_round<<<grid_n(net.nparams), 256, 0, s>>>(w.t); }
+    { ProfScope _ps("mlp_rows", s); mlp_rows<<<w.blocks, 64 * kRW, 0, s>>>(w.t); }
+    WgradArgs wa{w.t, w.slices, net.nparams, w.part};
+    { ProfScope _ps("mlp_wgrad", s); mlp_wgrad<<<ntiles * w.slices, 256, 0, s>>>(wa); }
+    UpdateArgs ua;
+    memset(&ua, 0, sizeof(ua));
+    ua.t = w.t;
+    ua.slices = w.slices;
+    ua.blocks = w.blocks;
+    ua.nparams = net.nparams;
+    ua.part = w.part;
+    ua.m = m;
+    ua.v = v;
+    ua.grad = grad;
+    ua.lr = lr;
+    ua.b1 = beta1;
+    ua.b2 = beta2;
+    ua.eps = eps;
+    ua.loss = loss;
+    { ProfScope _ps("mlp_update", s); mlp_update<<<grid_n(net.nparams), 256, 0, s>>>(ua); }
+    return check_launch("mlp_train_step");
 }

@@ -67,6 +67,9 @@ SIGNATURES = {
     "mlp_mse_grad": (_i32, [_u32, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "adam_step": (_i32, [_u64, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, C.c_float, _u32, _vp]),
     "adam_step_device": (_i32, [_u64, _vp, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float, _vp, _vp]),
+    "mlp_train_workspace_bytes": (_sz, [_vp, _u32]),
+    "mlp_train_step": (_i32, [_vp, _u32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, C.c_float, C.c_float, C.c_float,
+                              _vp, _vp, _vp, _vp, _sz, _vp]),
 }
 
 
@@ -526,6 +529,26 @@ def adam_step_device(params, grad, m, v, lr_dev, step_dev, beta1=0.9, beta2=0.99
     assert lr_dev.dtype == torch.float32 and step_dev.dtype == torch.int32
     _check(load().adam_step_device(params.numel(), _ptr(params), _ptr(grad), _ptr(m), _ptr(v), _ptr(lr_dev), beta1,
                                    beta2, eps, _ptr(step_dev), _stream(stream)))
+
+
+def mlp_train_workspace_bytes(shape, batch):
+    return int(load().mlp_train_workspace_bytes(C.byref(shape), batch))
+
+
+def mlp_train_step(shape, batch, params, x, target, m, v, lr_dev, step_dev, ws, *, rows=None, mask=None,
+                   col_weight=None, loss=None, grad=None, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    """One fused training step (forward, loss gradient, backward, Adam) in four
+    launches; returns the device loss (float32 [1]).  rows: int64 [batch]
+    device indices into x / target / mask, or None for the first `batch` rows."""
+    assert lr_dev.dtype == torch.float32 and step_dev.dtype == torch.int32
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    if rows is not None:
+        assert rows.dtype == torch.int64 and rows.numel() == batch
+    _check(load().mlp_train_step(C.byref(shape), batch, _ptr(params), _ptr(x), _ptr(target), _ptr(mask),
+                                 _ptr(col_weight), _ptr(rows), _ptr(m), _ptr(v), _ptr(lr_dev), beta1, beta2, eps,
+                                 _ptr(step_dev), _ptr(loss), _ptr(grad), _ptr(ws), ws.numel(), _stream(stream)))
+    return loss
 
 
 def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -103,3 +103,100 @@ def test_training_reduces_loss(sfg):
         if step in (1, 400):
             losses.append(float(loss.item()))
     assert losses[1] < 0.1 * losses[0], losses
+
+
+def _fused_step(sfg, shape, batch, params, x, t, rows=None, mask=None, cw=None, lr=1e-2):
+    import torch
+    p = params.clone()
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    grad = torch.empty_like(p)
+    lr_dev = torch.tensor([lr], dtype=torch.float32, device="cuda")
+    step_dev = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ws = sfg.workspace(sfg.mlp_train_workspace_bytes(shape, batch))
+    loss = sfg.mlp_train_step(shape, batch, p, x, t, m, v, lr_dev, step_dev, ws, rows=rows, mask=mask,
+                              col_weight=cw, grad=grad)
+    torch.cuda.synchronize()
+    assert int(step_dev.item()) == 1
+    return p, grad, float(loss.item())
+
+
+@pytest.mark.parametrize("shape_t,batch", [((10, 256, 34, 3), 1000), ((10, 256, 34, 3), 4096), ((10, 256, 34, 3), 1),
+                                           ((5, 70, 7, 2), 63), ((3, 40, 130, 1), 257)])
+def test_fused_step_matches_oracle(sfg, shape_t, batch):
+    """mlp_train_step: the gradient it applies equals the oracle's (forward,
+    loss gradient and backward in float64 with the same bf16 rounding points)
+    at the tolerances above, its loss the oracle's, and the parameters after
+    the step the oracle's Adam applied to that gradient."""
+    shape, params, x, t, g = _setup(sfg, shape_t, batch, 70 + batch)
+    p, grad, loss = _fused_step(sfg, shape, batch, g["params"], g["x"], g["t"])
+    yo, cache = omlp.forward(shape_t, params.astype(np.float64), x.astype(np.float64))
+    dyo, losso = omlp.mse_grad(yo, t.astype(np.float64))
+    go, _ = omlp.backward(shape_t, params.astype(np.float64), cache, dyo)
+    _close(grad.cpu().numpy(), go, 1e-2)
+    assert abs(loss - losso) <= 1e-3 * abs(losso), (loss, losso)
+    gpu_grad = grad.cpu().numpy().astype(np.float64)
+    po, _, _ = omlp.adam(params.astype(np.float64), gpu_grad, np.zeros_like(gpu_grad), np.zeros_like(gpu_grad), 1,
+                         lr=1e-2)
+    np.testing.assert_allclose(p.cpu().numpy(), po, rtol=1e-5, atol=1e-6)
+
+
+def test_fused_step_rows_mask_weights_equal_unfused(sfg):
+    """A shuffled batch (rows), a mask and column weights: the fused step's
+    gradient and loss equal the unfused kernels' on the gathered batch
+    (float32 summation order only)."""
+    import torch
+    shape_t, batch, N = (10, 256, 34, 3), 777, 2000
+    shape, params, _, _, g = _setup(sfg, shape_t, 1, 9)
+    rng = np.random.default_rng(10)
+    X = torch.tensor(rng.normal(size=(N, 10)).astype(np.float32)).cuda()
+    T = torch.tensor(rng.normal(size=(N, 34)).astype(np.float32)).cuda()
+    M = torch.tensor((rng.uniform(size=(N, 34)) > 0.2).astype(np.float32)).cuda()
+    cw = torch.tensor(rng.uniform(0.2, 2.0, size=34).astype(np.float32)).cuda()
+    rows = torch.tensor(rng.permutation(N)[:batch]).cuda()
+    _, grad, loss = _fused_step(sfg, shape, batch, g["params"], X, T, rows=rows, mask=M, cw=cw)
+    ws = sfg.workspace(sfg.mlp_workspace_bytes(shape, batch))
+    y = sfg.mlp_forward(shape, g["params"], X[rows].contiguous(), ws)
+    dy, loss_u = sfg.mlp_mse_grad(y, T[rows].contiguous(), sfg.workspace(4 * batch), mask=M[rows].contiguous(),
+                                  col_weight=cw)
+    grad_u, _ = sfg.mlp_backward(shape, g["params"], dy, ws)
+    torch.cuda.synchronize()
+    _close(grad.cpu().numpy(), grad_u.cpu().numpy(), 1e-3)
+    assert abs(loss - float(loss_u.item())) <= 1e-5 * abs(loss)
+
+
+def test_fused_step_graph_replays_equal_eager(sfg):
+    """The fused step captured into a HIP graph: every replay, with eager
+    library work and synchronisations between replays, equals the eager
+    step on the same state."""
+    import torch
+    shape_t, batch = (10, 256, 34, 3), 512
+    shape, params, x, t, g = _setup(sfg, shape_t, batch, 12)
+    ws = sfg.workspace(sfg.mlp_train_workspace_bytes(shape, batch))
+    lr_dev = torch.tensor([3e-3], dtype=torch.float32, device="cuda")
+
+    def state():
+        return (g["params"].clone(), torch.zeros_like(g["params"]), torch.zeros_like(g["params"]),
+                torch.zeros(1, dtype=torch.int32, device="cuda"))
+
+    pe, me, ve, se = state()
+    eager = []
+    for _ in range(3):
+        sfg.mlp_train_step(shape, batch, pe, g["x"], g["t"], me, ve, lr_dev, se, ws)
+        eager.append(pe.clone())
+    pg, mg, vg, sg_ = state()
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    sfg.mlp_train_step(shape, batch, pg, g["x"], g["t"], mg, vg, lr_dev, sg_, ws, loss=loss)  # eager first step
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        sfg.mlp_train_step(shape, batch, pg, g["x"], g["t"], mg, vg, lr_dev, sg_, ws, loss=loss)
+    torch.cuda.synchronize()
+    # capture does not run the step: state is still after one step
+    assert torch.equal(pg, eager[0])
+    for rep in range(2):
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(pg, eager[rep + 1]), rep
+        sfg.mlp_forward(shape, pg, g["x"], sfg.workspace(sfg.mlp_workspace_bytes(shape, batch)))  # eager work between
+        torch.cuda.synchronize()
+    assert int(sg_.item()) == 3
