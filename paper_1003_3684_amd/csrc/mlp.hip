@@ -29,17 +29,10 @@ constexpr int kTile = 64;   // block tile (M and N)
 constexpr int kKStep = 32;  // K per MFMA step
 constexpr int kPad = 8;     // LDS row padding (bf16 elements)
 
-// float -> bfloat16, round to nearest even (NaN stays NaN).
-__device__ __forceinline__ uint16_t f2bf_bits(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ bf16 f2bf(float f) {
-    const uint16_t b = f2bf_bits(f);
-    return __builtin_bit_cast(bf16, b);
-}
+// float -> bfloat16, round to nearest even (NaN stays NaN): the conversion
+// instruction of the matrix-core generation (v_cvt_pk_bf16_f32, which rounds
+// in the wave's rounding mode, nearest even by default).
+__device__ __forceinline__ bf16 f2bf(float f) { return (bf16)f; }
 __device__ __forceinline__ float bf2f(bf16 h) {
     const uint16_t b = __builtin_bit_cast(uint16_t, h);
     return __uint_as_float((uint32_t)b << 16);
@@ -135,7 +128,10 @@ __global__ __launch_bounds__(256) void gemm_bf16(const bf16 *__restrict__ A, int
             }
 }
 
-__device__ __forceinline__ float sigmoidf_(float z) { return 1.0f / (1.0f + expf(-z)); }
+// 1 / (1 + e^-z) with the hardware exponential (2^x of z log2 e) and
+// reciprocal: relative error a few float32 ulps, far below the bf16 rounding
+// applied to every activation; saturates to exactly 0 and 1.
+__device__ __forceinline__ float sigmoidf_(float z) { return __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 // bf16 copy of every weight matrix of the parameter vector.
 __global__ void round_weights(const float *p, bf16 *wb, uint64_t n) {
@@ -309,7 +305,10 @@ struct TrainArgs {
     int dims[kFMaxL + 1];  // dims[0] = d_in, dims[l + 1] = outputs of layer l
     size_t w_off[kFMaxL], b_off[kFMaxL];
     float *params;
-    const bf16 *wb, *wbt;  // bf16 weights, per layer [out][in] and [in][out], at w_off
+    // bf16 weights of layer l, zero-padded: wb + wp_off[l] is [pad16(out)][pad32(in)],
+    // wbt + wtp_off[l] is [pad16(in)][pad32(out)] (W transposed)
+    const bf16 *wb, *wbt;
+    size_t wp_off[kFMaxL], wtp_off[kFMaxL];
     const float *x, *target, *mask, *cw;
     const int64_t *rows;  // batch row r is row rows[r] of x, target and mask (null: row r)
     bf16 *xb[kFMaxL];     // [pad16(dims[l])][Bp] layer inputs
@@ -325,42 +324,36 @@ __device__ __forceinline__ int round32(int x) { return (x + 31) & ~31; }
 
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 
-// bf16 weights: wb[w_off + n * in + k] = bf16(W[n][k]), wbt[w_off + k * out + n] = the same.
+// The zero-padded bf16 weight copies wb and wbt of every layer.
 __global__ void mlp_round(TrainArgs a) {
     for (int l = 0; l < a.L; ++l) {
-        const int in = a.dims[l], out = a.dims[l + 1], n = in * out;
+        const int in = a.dims[l], out = a.dims[l + 1];
+        const int ki = round32(in), ko = round32(out), n1 = round16(out) * ki, n2 = round16(in) * ko;
         const float *W = a.params + a.w_off[l];
-        bf16 *wb = const_cast<bf16 *>(a.wb) + a.w_off[l], *wbt = const_cast<bf16 *>(a.wbt) + a.w_off[l];
-        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-            const bf16 v = f2bf(W[i]);
-            wb[i] = v;
-            wbt[(i % in) * out + i / in] = v;
+        bf16 *wb = const_cast<bf16 *>(a.wb) + a.wp_off[l], *wbt = const_cast<bf16 *>(a.wbt) + a.wtp_off[l];
+        for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n1 + n2; i += gridDim.x * blockDim.x) {
+            if (i < n1) {
+                const int n = i / ki, k = i % ki;
+                wb[i] = f2bf(n < out && k < in ? W[n * in + k] : 0.f);
+            } else {
+                const int k = (i - n1) / ko, n = (i - n1) % ko;
+                wbt[i - n1] = f2bf(n < out && k < in ? W[n * in + k] : 0.f);
+            }
         }
     }
 }
 
-// 8 consecutive bf16 of row n of a [rows][ld] matrix from column k (k a
-// multiple of 8); zero outside [0, rows) x [0, cols).  vec: M is 16-byte
-// aligned and ld a multiple of 8.
-__device__ __forceinline__ bf16x8 frag(const bf16 *M, int ld, int rows, int cols, int n, int k, bool vec) {
-    if (vec && n < rows && k + 8 <= cols) return *reinterpret_cast<const bf16x8 *>(M + (size_t)n * ld + k);
-    bf16x8 f;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) f[e] = (n < rows && k + e < cols) ? M[(size_t)n * ld + k + e] : f2bf(0.f);
-    return f;
-}
-
 // C (64 rows x N) = A (64 x K, bf16 in LDS, row stride kFMax + 8) * M^T with
-// M (N x K) bf16 row-major (ld = Kreal).  Wave w of the kRW waves takes the
-// column tiles w and w + kRW (N <= 256).  All of the wave's M fragments for
-// the layer (K <= 256: at most 8 k-steps) are loaded before the first
-// product, so a layer costs one round trip to L2 instead of one per k-step.
-__device__ __forceinline__ void rows_gemm(const bf16 (*sA)[kFMax + 8], int K, const bf16 *M, int N, int Kreal,
+// M [pad16(N)][K] the zero-padded bf16 weights (K a multiple of 32).  Wave w
+// of the kRW waves takes the column tiles w and w + kRW (N <= 256).  All of
+// the wave's M fragments for the layer (K <= 256: at most 8 k-steps) are
+// loaded before the first product, so a layer costs one round trip to L2
+// instead of one per k-step.
+__device__ __forceinline__ void rows_gemm(const bf16 (*sA)[kFMax + 8], int K, const bf16 *M, int N,
                                           floatx4 (&acc)[4][kCT]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int r = lane % 16, kq = 8 * (lane / 16);
     const int ntiles = (N + 15) / 16;
-    const bool vec = ((uintptr_t)M % 16) == 0 && Kreal % 8 == 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -371,7 +364,8 @@ __device__ __forceinline__ void rows_gemm(const bf16 (*sA)[kFMax + 8], int K, co
 #pragma unroll
         for (int j = 0; j < kCT; ++j) {
             const int ct = w + kRW * j;
-            if (st * kKStep < K && ct < ntiles) fb[st][j] = frag(M, Kreal, N, Kreal, 16 * ct + r, st * kKStep + kq, vec);
+            if (st * kKStep < K && ct < ntiles)
+                fb[st][j] = *reinterpret_cast<const bf16x8 *>(M + (size_t)(16 * ct + r) * K + st * kKStep + kq);
         }
 #pragma unroll
     for (int st = 0; st < kFMax / kKStep; ++st) {
@@ -461,7 +455,7 @@ __global__ __launch_bounds__(64 * kRW) void mlp_rows(TrainArgs a) {
             bj[j] = c < out ? a.params[a.b_off[l] + c] : 0.f;
             cwj[j] = (last && c < out && a.cw) ? a.cw[c] : 1.f;
         }
-        rows_gemm(sA, round32(in), a.wb + a.w_off[l], out, in, acc);
+        rows_gemm(sA, round32(in), a.wb + a.wp_off[l], out, acc);
         __syncthreads();  // every wave is done reading sA
         if (!last) {
 #pragma unroll
@@ -541,8 +535,8 @@ __global__ __launch_bounds__(64 * kRW) void mlp_rows(TrainArgs a) {
     for (int l = L - 1; l >= 1; --l) {
         const int out = a.dims[l + 1], in = a.dims[l];
         const int npad = round32(in), ntiles = (in + 15) / 16;
-        // dH (64 x in) = dZb (64 x out) Wb (out x in): M = Wb^T, [in][out]
-        rows_gemm(sA, round32(out), a.wbt + a.w_off[l], in, out, acc);
+        // dH (64 x in) = dZb (64 x out) Wb (out x in): M = Wb^T
+        rows_gemm(sA, round32(out), a.wbt + a.wtp_off[l], in, acc);
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < kCT; ++j) {
@@ -909,8 +903,16 @@ TrainWs carve_train(const Net &net, uint32_t B, void *base) {
     w.t.B = (int)B;
     w.t.Bp = Bp;
     w.t.dims[0] = net.layer[0].in;
-    w.t.wb = c.take<bf16>(net.nparams);
-    w.t.wbt = c.take<bf16>(net.nparams);
+    size_t wp = 0, wtp = 0;
+    for (int l = 0; l < net.L; ++l) {
+        const size_t in = net.layer[l].in, out = net.layer[l].out;
+        w.t.wp_off[l] = wp;
+        w.t.wtp_off[l] = wtp;
+        wp += round16(out) * ((in + 31) & ~(size_t)31);
+        wtp += round16(in) * ((out + 31) & ~(size_t)31);
+    }
+    w.t.wb = c.take<bf16>(wp);
+    w.t.wbt = c.take<bf16>(wtp);
     for (int l = 0; l < net.L; ++l) {
         const size_t pin = round16(net.layer[l].in), pout = round16(net.layer[l].out);
         w.t.dims[l + 1] = net.layer[l].out;
@@ -961,7 +963,7 @@ extern "C" int mlp_train_step(const sfg_mlp_shape *shape, uint32_t batch, float 
     int ntiles = 0;
     for (int l = 0; l < net.L; ++l)
         ntiles += ((net.layer[l].out + kTile - 1) / kTile) * ((net.layer[l].in + kTile - 1) / kTile);
-    { ProfScope _ps("mlp_round", s); mlp_round<<<grid_n(net.nparams), 256, 0, s>>>(w.t); }
+    { ProfScope _ps("mlp_round", s); mlp_round<<<grid_n(2 * net.nparams), 256, 0, s>>>(w.t); }
     { ProfScope _ps("mlp_rows", s); mlp_rows<<<w.blocks, 64 * kRW, 0, s>>>(w.t); }
     WgradArgs wa{w.t, w.slices, net.nparams, w.part};
     { ProfScope _ps("mlp_wgrad", s); mlp_wgrad<<<ntiles * w.slices, 256, 0, s>>>(wa); }

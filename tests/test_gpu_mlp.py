@@ -200,3 +200,57 @@ def test_fused_step_graph_replays_equal_eager(sfg):
         sfg.mlp_forward(shape, pg, g["x"], sfg.workspace(sfg.mlp_workspace_bytes(shape, batch)))  # eager work between
         torch.cuda.synchronize()
     assert int(sg_.item()) == 3
+
+
+def _rne_bf16(v):
+    """float32 -> bfloat16 -> float64 by the definition of rounding to nearest
+    even on the bit pattern (finite inputs)."""
+    u = v.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _rounding_cases(rng, n):
+    """n float32 values in [2^-8, 2^9) of either sign: random patterns, exact
+    ties with even and odd upper halves, and the neighbours of ties."""
+    hi = (rng.integers(0x3B80, 0x4400, size=n) | (rng.integers(0, 2, size=n) << 15)).astype(np.uint32)
+    lo = rng.choice(np.array([0x8000, 0x7FFF, 0x8001, 0x0000, 0xFFFF, 0x0001], dtype=np.uint32), size=n)
+    lo = np.where(rng.uniform(size=n) < 0.3, rng.integers(0, 1 << 16, size=n).astype(np.uint32), lo)
+    return ((hi << 16) | lo).astype(np.uint32).view(np.float32)
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_input_rounding_is_nearest_even(sfg, fused):
+    """At batch one the first layer's weight gradient is dZb_0[j] * bf16(x_i),
+    a product of two bf16 values and so exact in float32: its ratio to the
+    entry of x_0 = 1 is bf16(x_i) itself.  Every such ratio equals rounding to
+    nearest even by its definition, ties (both parities) and their
+    neighbours included, in the unfused kernels and in the fused step."""
+    import torch
+    rng = np.random.default_rng(77 + fused)
+    D = 256 if fused else 4096
+    shape_t = (D, 16, 8, 1)
+    shape = sfg.mlp_shape(*shape_t)
+    P = sfg.mlp_param_count(shape)
+    checked = 0
+    for call in range(8 if fused else 2):
+        params = rng.normal(0, 1.0 / D, size=P).astype(np.float32)
+        x = np.concatenate([[np.float32(1.0)], _rounding_cases(rng, D - 1)]).astype(np.float32)[None, :]
+        t = rng.normal(size=(1, 8)).astype(np.float32)
+        pt, xt, tt = torch.tensor(params).cuda(), torch.tensor(x).cuda(), torch.tensor(t).cuda()
+        if fused:
+            _, grad, _ = _fused_step(sfg, shape, 1, pt, xt, tt)
+            grad = grad.cpu().numpy()
+        else:
+            ws = sfg.workspace(sfg.mlp_workspace_bytes(shape, 1))
+            y = sfg.mlp_forward(shape, pt, xt, ws)
+            dy, _ = sfg.mlp_mse_grad(y, tt, sfg.workspace(4))
+            grad, _ = sfg.mlp_backward(shape, pt, dy, ws)
+            torch.cuda.synchronize()
+            grad = grad.cpu().numpy()
+        W0 = grad[:16 * D].reshape(16, D).astype(np.float64)
+        j = int(np.argmax(np.abs(W0[:, 0])))
+        assert W0[j, 0] != 0.0
+        np.testing.assert_array_equal(W0[j] / W0[j, 0], _rne_bf16(x[0]), err_msg=f"call {call}")
+        checked += D
+    assert checked >= 2000
