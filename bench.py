@@ -199,9 +199,10 @@ def main():
     ap.add_argument("--cpu-full", action="store_true",
                     help="also time the oracle on the 2^27-vertex PBA configuration in full (minutes)")
     ap.add_argument("--no-extras", action="store_true", help="skip the PBA and ensemble extras")
-    ap.add_argument("--only", choices=("pba", "cpu", "surrogate"), default=None,
+    ap.add_argument("--only", choices=("pba", "cpu", "surrogate", "mlp"), default=None,
                     help="run only one part and print its JSON: 'pba' = PBA generation at 2^27 and 2^30 vertices "
-                         "with per-kernel times (for profiling runs); 'cpu' = the CPU oracle baseline")
+                         "with per-kernel times (for profiling runs); 'cpu' = the CPU oracle baseline; 'mlp' = the "
+                         "surrogate's training step, fused and unfused")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy three times (the reference kernel of known "
                          "size for scaling the HBM byte counters) and exit")
@@ -227,6 +228,12 @@ def main():
         from paper_1003_3684_amd import workloads as wl
         sfg.load()
         print(json.dumps({"surrogate": _bench_surrogate(sfg, wl, torch)}), flush=True)
+        return
+    if args.only == "mlp":
+        import torch
+        from paper_1003_3684_amd import native as sfg
+        sfg.load()
+        print(json.dumps({"mlp_step": _bench_mlp(sfg, torch)}), flush=True)
         return
     if args.only == "pba":
         import torch

@@ -204,7 +204,8 @@ int pba_generate(uint64_t n, uint32_t m, uint32_t num_parts, double p_inter, con
  *                  one.
  * workspace:       device, edges_to_csr_workspace_bytes(...) bytes.
  * Errors: EINVAL (n == 0, bad flags, NULL buffers); ERANGE (ids or sizes do
- * not fit); ENOSPACE.  Ids outside [0, n) are not detected (the caller's
+ * not fit: n > 2^32, more than 2^34 entries -- edges, doubled when
+ * symmetrized); ENOSPACE.  Ids outside [0, n) are not detected (the caller's
  * contract): the output is then unspecified, but no kernel writes or reads
  * outside the buffers on their account.
  * The sort's passes wait on earlier workgroups of the same launch (decoupled
@@ -375,8 +376,8 @@ int kron_perturbed(uint32_t n0, const float *seed_matrix, uint32_t k, double p_a
  * workspace:   device, kron_xor_random_workspace_bytes(...).
  * Errors: EINVAL (n0 outside [2, 64], k == 0, a negative / NaN / infinite
  * entry, no edge in the seed, bad id_bytes, NULL buffers, graph_id >= 2^24);
- * ERANGE (n0^k > 2^31, e0^k or num_random > 2^40, ids beyond int32 with
- * id_bytes 4); ENOSPACE.  kron_xor_random_workspace_bytes returns 0 for
+ * ERANGE (n0^k > 2^31, e0^k or num_random > 2^40, e0^k + num_random > 2^34,
+ * ids beyond int32 with id_bytes 4); ENOSPACE.  kron_xor_random_workspace_bytes returns 0 for
  * arguments that would be rejected.
  * ---------------------------------------------------------------------- */
 size_t kron_xor_random_workspace_bytes(uint32_t n0, const float *seed_matrix, uint32_t k, uint64_t num_random,

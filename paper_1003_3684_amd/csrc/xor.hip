@@ -58,6 +58,8 @@ int xor_sizes(uint32_t n0, const float *seed_matrix, uint32_t k, uint64_t num_ra
     }
     if (id_bytes == 4 && n - 1 > 0x7FFFFFFFull) return fail(SFG_ERANGE, "kron_xor_random: ids do not fit int32");
     if (num_random > (1ull << 40)) return fail(SFG_ERANGE, "kron_xor_random: num_random above 2^40");
+    // The sort takes one workgroup per tile of entries (see edges_to_csr).
+    if (epk + num_random > (1ull << 34)) return fail(SFG_ERANGE, "kron_xor_random: more than 2^34 entries");
     z->n = n;
     z->epk = epk;
     z->total = epk + num_random;

@@ -120,3 +120,18 @@ def test_csr_sorted_inputs(sfg, orc, order, flags):
     src[1::89] = src[0:-1:89][: len(src[1::89])]
     for ib in (4, 8):
         _check(sfg, orc, n, src, dst, flags, ib)
+
+
+def test_entry_count_limit(sfg):
+    """More than 2^34 entries (edges, doubled when symmetrized) is ERANGE,
+    found before any buffer is touched: with one workgroup per tile a
+    dispatch's work-item count stays below 2^32."""
+    import torch
+    lib = sfg.load()
+    t = torch.zeros(64, dtype=torch.int64, device="cuda")
+    p = t.data_ptr()
+    for num_edges, flags in (((1 << 34) + 1, 0), ((1 << 33) + 1, sfg.CSR_SYMMETRIZE)):
+        rc = lib.edges_to_csr(1000, num_edges, p, p, 8, flags, p, p, None, None, p, 1 << 62, None)
+        assert rc == sfg.SFG_ERANGE, (num_edges, flags, rc)
+    torch.cuda.synchronize()
+    assert int(t.abs().sum().item()) == 0
