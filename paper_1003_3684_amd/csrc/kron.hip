@@ -26,6 +26,10 @@ namespace sfg {
 namespace {
 
 constexpr int kBlock = 256;
+// The register-path sampler's LDS (byte counters, guide and packing tables,
+// about 53 KB) allows three workgroups per CU: 1,024-thread workgroups give
+// it the full 32 waves per CU to hide its LDS latency with.
+constexpr int kFastBlock = 1024;
 
 }  // namespace
 
@@ -125,7 +129,7 @@ constexpr uint32_t kStraddle = 0x80;
 // into the global rows once per workgroup.  The counts are exact integers, so
 // the result does not depend on the order in which lanes add them.
 template <typename IdT, typename AccT, bool POW2, int NT, bool CNT>
-__global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__restrict__ src, IdT *__restrict__ dst) {
+__global__ __launch_bounds__(kFastBlock) void kron_sample_fast(FastArgs a, IdT *__restrict__ src, IdT *__restrict__ dst) {
     // With few thresholds the comparisons are cheaper than the table.
     constexpr bool kGuide = NT > 3;
     __shared__ uint8_t s_guide[kGuide ? 2 * kGuideSize : 1];  // row digits | kStraddle, then column digits
@@ -136,11 +140,11 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
     __shared__ uint8_t s_pack[CNT && POW2 ? kPackTabMax : 1];
     const uint32_t copy = threadIdx.x % kCountCopies;
     if (CNT)
-        for (uint32_t i = threadIdx.x; i < kCountRows * 256 * kCountCopies; i += kBlock) s_cnt[i] = 0;
+        for (uint32_t i = threadIdx.x; i < kCountRows * 256 * kCountCopies; i += kFastBlock) s_cnt[i] = 0;
     if (CNT && POW2 && a.pack_groups)
-        for (uint32_t i = threadIdx.x; i < (1u << a.pack_bits); i += kBlock) s_pack[i] = (uint8_t)a.pack_tab[i];
+        for (uint32_t i = threadIdx.x; i < (1u << a.pack_bits); i += kFastBlock) s_pack[i] = (uint8_t)a.pack_tab[i];
     if (kGuide) {
-        for (uint32_t i = threadIdx.x; i < kGuideSize; i += kBlock) {
+        for (uint32_t i = threadIdx.x; i < kGuideSize; i += kFastBlock) {
             const uint32_t lo = i << (32 - kGuideBits), hi = lo | ((1u << (32 - kGuideBits)) - 1u);
             const uint32_t blo = bucket_of<NT>(lo, a.tm1), bhi = bucket_of<NT>(hi, a.tm1);
             const uint32_t rd = (uint32_t)(a.lut_row >> (4 * blo)) & 15u, cd = (uint32_t)(a.lut_col >> (4 * blo)) & 15u;
@@ -186,8 +190,8 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
     };
     // Whole blocks of four levels first (no per-level test), then the rest.
     const uint32_t full = a.k / 4, rest = a.k % 4;
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < a.num_edges; i += stride) {
+    const uint64_t stride = (uint64_t)gridDim.x * kFastBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kFastBlock + threadIdx.x; i < a.num_edges; i += stride) {
         AccT u = 0, v = 0;
         const uint64_t e = a.e_begin + i;  // the edge's index in the whole graph
         const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
@@ -224,7 +228,7 @@ __global__ __launch_bounds__(kBlock) void kron_sample_fast(FastArgs a, IdT *__re
     }
     if (CNT) {
         __syncthreads();
-        for (uint32_t i = threadIdx.x; i < (uint32_t)a.rows * 256; i += kBlock) {
+        for (uint32_t i = threadIdx.x; i < (uint32_t)a.rows * 256; i += kFastBlock) {
             const uint32_t slot = ((i >> 8) % (uint32_t)a.row_mod) * 256 + (i & 255u);
             uint32_t t = 0;
 #pragma unroll
@@ -435,16 +439,22 @@ int grid_for(uint64_t items) {
     return (int)std::max<uint64_t>(1, std::min(want, cap));
 }
 
+int grid_fast(uint64_t items) {
+    const uint64_t want = (items + kFastBlock - 1) / kFastBlock;
+    const uint64_t cap = (uint64_t)device_cu_count() * 4;
+    return (int)std::max<uint64_t>(1, std::min(want, cap));
+}
+
 template <typename IdT, typename AccT, bool POW2, bool CNT>
 void launch_fast(const FastArgs &a, uint32_t nt, void *src, void *dst, hipStream_t s) {
-    const int g = grid_for(a.num_edges);
+    const int g = grid_fast(a.num_edges);
     IdT *S = static_cast<IdT *>(src), *D = static_cast<IdT *>(dst);
     if (nt <= 3)
-        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 3, CNT><<<g, kBlock, 0, s>>>(a, S, D); }
+        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 3, CNT><<<g, kFastBlock, 0, s>>>(a, S, D); }
     else if (nt <= 8)
-        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 8, CNT><<<g, kBlock, 0, s>>>(a, S, D); }
+        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 8, CNT><<<g, kFastBlock, 0, s>>>(a, S, D); }
     else
-        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 15, CNT><<<g, kBlock, 0, s>>>(a, S, D); }
+        { ProfScope _ps("kron_sample", s); kron_sample_fast<IdT, AccT, POW2, 15, CNT><<<g, kFastBlock, 0, s>>>(a, S, D); }
 }
 
 template <typename IdT, typename AccT>
@@ -488,8 +498,8 @@ bool count_ok(const ByteCount &bc, uint64_t count, int id_bytes) {
     if (bc.pack_groups && (bc.pack_groups < 1 || bc.pack_bits < 1 || bc.pack_bits > 12 || !bc.pack_tab || bc.key_sym ||
                            (1 << bc.pack_bits) > kPackTabMax))
         return false;
-    const uint64_t threads = (uint64_t)grid_for(count) * kBlock;
-    const uint64_t per_group = (count + threads - 1) / threads * kBlock;
+    const uint64_t threads = (uint64_t)grid_fast(count) * kFastBlock;
+    const uint64_t per_group = (count + threads - 1) / threads * kFastBlock;
     return 2 * per_group < (1ull << 32);
 }
 
