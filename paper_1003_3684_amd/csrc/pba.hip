@@ -492,6 +492,19 @@ template <typename IdT> __global__ __launch_bounds__(kSubThreads) void pba_subst
     const uint64_t last = std::min<uint64_t>(len, first + p.CT);
     const uint32_t *hrow = a.H + p.H0 + ((uint64_t)q * p.T1 + tau) * P;
     const uint64_t *lbase = a.sbase + p.seg0;
+    // Labels of this wave's quarter of a sub-tile.  Each sub-tile's labels
+    // are loaded while the previous one is gathered and written (the first
+    // sub-tile's while the list positions are set up).
+    uint32_t lr[kSubSteps];
+    auto load_labels = [&](uint64_t p0) {
+        const uint32_t ns = (uint32_t)std::min<uint64_t>(kSubSlots, last - p0);
+#pragma unroll
+        for (int st = 0; st < kSubSteps; ++st) {
+            const uint32_t i = (uint32_t)w * kSubWave + (uint32_t)st * 64 + lane;
+            lr[st] = i < ns ? a.lab[b0 + p0 + i] : 0u;
+        }
+    };
+    if (first < last) load_labels(first);
     for (uint32_t l = tid; l < P; l += kSubThreads) s_cur[l] = lbase[l] + hrow[l];
     __syncthreads();
     uint32_t lbits = 0;
@@ -509,15 +522,12 @@ template <typename IdT> __global__ __launch_bounds__(kSubThreads) void pba_subst
     for (uint64_t pos0 = first; pos0 < last; pos0 += kSubSlots) {
         const uint32_t nsub = (uint32_t)std::min<uint64_t>(kSubSlots, last - pos0);
         for (uint32_t l = lane; l < P; l += 64) wcnt[l] = 0;
-        // Labels of this wave's quarter, and their stable ranks inside it.
-        uint32_t lr[kSubSteps], rr[kSubSteps];
+        // This wave's labels, and their stable ranks inside its quarter.
+        uint32_t rr[kSubSteps];
 #pragma unroll
         for (int st = 0; st < kSubSteps; ++st) {
             const uint32_t i = (uint32_t)w * kSubWave + (uint32_t)st * 64 + lane;
-            const bool valid = i < nsub;
-            const uint32_t l = valid ? a.lab[b0 + pos0 + i] : 0u;
-            if (valid) s_lab[i] = (uint16_t)l;
-            lr[st] = l;
+            if (i < nsub) s_lab[i] = (uint16_t)lr[st];
         }
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -598,6 +608,7 @@ template <typename IdT> __global__ __launch_bounds__(kSubThreads) void pba_subst
                 const uint32_t l = s_lab[slot[k]];
                 v[k] = i < nsub ? a.sel[s_cur[l] + (i - s_off[l])] : 0u;
             }
+            if (pos0 + kSubSlots < last) load_labels(pos0 + kSubSlots);
 #pragma unroll
             for (int k = 0; k < kPerThread; ++k)
                 if ((uint32_t)k * kSubThreads + tid < nsub) s_val[slot[k]] = v[k];
