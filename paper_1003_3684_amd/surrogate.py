@@ -84,15 +84,22 @@ class Surrogate:
         self.batch = batch
         self.ws = sfg.workspace(sfg.mlp_workspace_bytes(self.shape, batch))
         self.lws = sfg.workspace(4 * batch)
+        # The fused training step's workspace (None when the network is wider
+        # than the fused step takes).
+        tb = sfg.mlp_train_workspace_bytes(self.shape, batch)
+        self.tws = sfg.workspace(tb) if tb > 0 else None
         self.mu = np.zeros(D_OUT, np.float32)
         self.sd = np.ones(D_OUT, np.float32)
 
-    def fit(self, X, Y, M, epochs=30, lr=1e-3, seed=0, col_weight=None, graph=True):
+    def fit(self, X, Y, M, epochs=30, lr=1e-3, seed=0, col_weight=None, graph=True, fused=True):
         """Adam on standardized targets over full batches; returns the
-        per-epoch mean loss.  A training step is: gather the batch, forward,
-        loss gradient, backward, Adam.  The learning rate (cosine schedule)
-        and the step counter live in device memory, so with graph=True the
-        step is captured once into a HIP graph after a first eager step and
+        per-epoch mean loss.  A training step is forward, loss gradient,
+        backward and Adam over the batch's rows: with fused=True (and a
+        network the fused step takes) one mlp_train_step, which reads the
+        rows through the shuffled index list; otherwise the batch is gathered
+        and the unfused kernels run.  The learning rate (cosine schedule) and
+        the step counter live in device memory, so with graph=True the step
+        is captured once into a HIP graph after a first eager step and
         replayed; the result is bit-identical to the eager loop."""
         rng = np.random.default_rng(seed)
         Mb = M.astype(bool)
@@ -120,7 +127,14 @@ class Surrogate:
         step_dev = torch.tensor([self.step], dtype=torch.int32, device=dev)
         loss_acc = torch.zeros(1, dtype=torch.float32, device=dev)
 
+        fused = fused and self.tws is not None
+
         def step():
+            if fused:
+                sfg.mlp_train_step(self.shape, B, self.params, Xg, Yg, self.m, self.v, lr_dev, step_dev, self.tws,
+                                   rows=idx, mask=Mg, col_weight=cw, loss=loss)
+                loss_acc.add_(loss)
+                return
             torch.index_select(Xg, 0, idx, out=xs)
             torch.index_select(Yg, 0, idx, out=ys)
             torch.index_select(Mg, 0, idx, out=ms)
