@@ -343,7 +343,18 @@ __global__ __launch_bounds__(256) void pba_count(CountArgs a) {
     const uint64_t b0 = a.base1[s], len = a.base1[s + 1] - b0;
     const uint64_t first = (uint64_t)tau * p.CT;
     const uint64_t last = std::min<uint64_t>(len, first + p.CT);
-    for (uint64_t j = first + threadIdx.x; j < last; j += 256) atomicAdd(&s_h[a.lab[b0 + j]], 1u);
+    // Eight labels per thread in flight, then their counts.
+    for (uint64_t j0 = first + threadIdx.x; j0 < last; j0 += 256 * 8) {
+        uint32_t l[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint64_t j = j0 + (uint64_t)u * 256;
+            l[u] = j < last ? a.lab[b0 + j] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (j0 + (uint64_t)u * 256 < last) atomicAdd(&s_h[l[u]], 1u);
+    }
     __syncthreads();
     uint32_t *row = a.H + p.H0 + ((uint64_t)q * p.T1 + tau) * p.P;
     for (uint32_t l = threadIdx.x; l < p.P; l += 256) row[l] = s_h[l];
