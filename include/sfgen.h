@@ -98,9 +98,11 @@ int sfg_profile_query(const char *name, uint64_t *launches, double *total_ms);
  * k:             number of Kronecker levels; vertex ids lie in [0, n0^k).
  * mode SFG_KRON_SAMPLE: the stochastic model.  Edge e draws one cell per
  *     level, most significant level first, each with probability
- *     initiator[r][c] / sum(initiator); level l uses 32-bit word (l mod 4) of
- *     the Philox block (e, l / 4, tag 1).  A cell is chosen by comparing the
- *     word against binary64 cumulative thresholds floor(S_c / T * 2^32).
+ *     initiator[r][c] / sum(initiator); level l takes a 24-bit uniform U
+ *     from the Philox block (e, l / 5, tag 1): the top 24 bits of word
+ *     (l mod 5) for l mod 5 < 4, else the low bytes of words 0, 1, 2 (most
+ *     significant first).  The cell is #{c : 256 U >= floor(S_c / T * 2^32)},
+ *     binary64 cumulative thresholds.
  *     Row digits make the source id, column digits the destination id.
  *     Self-loops and repeated edges are kept.  Requires n0 <= 16.
  * mode SFG_KRON_ENUMERATE: the paper's deterministic Kronecker power.  The

@@ -100,10 +100,13 @@ def categorical_thresholds(W) -> np.ndarray:
 
 
 def cell_probabilities(W) -> np.ndarray:
-    """Exact probability of each cell under the 32-bit thresholds."""
-    thr = categorical_thresholds(W).astype(np.float64)
-    prev = np.concatenate([[0.0], thr[:-1]])
-    return (thr - prev) / 2.0 ** 32
+    """Exact probability of each cell for a level's 24-bit uniform U: cell c
+    takes the U with thr[c - 1] <= 256 U < thr[c], i.e. U in
+    [ceil(thr[c - 1] / 256), ceil(thr[c] / 256))."""
+    thr = categorical_thresholds(W).astype(np.uint64)
+    up = ((thr + np.uint64(255)) // np.uint64(256)).astype(np.float64)
+    prev = np.concatenate([[0.0], up[:-1]])
+    return (up - prev) / 2.0 ** 24
 
 
 # --------------------------------------------------------------------- Kronecker

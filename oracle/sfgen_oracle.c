@@ -121,10 +121,19 @@ static uint32_t cell_of(uint32_t w, const uint64_t *thr, uint32_t C)
  * gives every cell (u, v) of the n0^k x n0^k matrix the probability
  * prod_l W[u_l][v_l] / T^k (Kronecker product section; the probabilistic
  * model of Leskovec et al. cited in Related Work).  Each edge descends k
- * levels, most significant digit first; level l reads word (l mod 4) of the
- * Philox block (e, l / 4, KRON).  Edges e in [e_begin, e_end) are written to
- * src[e - e_begin], dst[e - e_begin].  Self-loops and duplicates are kept.
+ * levels, most significant digit first.  Level l takes a 24-bit uniform U
+ * from the Philox block (e, l / 5, KRON): for l mod 5 = i < 4 the top 24
+ * bits of word i, for l mod 5 = 4 the low bytes of words 0, 1 and 2 (most
+ * significant first); the cell is the one the 32-bit thresholds give to
+ * U * 256.  Edges e in [e_begin, e_end) are written to src[e - e_begin],
+ * dst[e - e_begin].  Self-loops and duplicates are kept.
  * ------------------------------------------------------------------------- */
+static uint32_t level_uniform24(const uint32_t blk[4], uint32_t i)
+{
+    if (i < 4) return blk[i] >> 8;
+    return ((blk[0] & 255u) << 16) | ((blk[1] & 255u) << 8) | (blk[2] & 255u);
+}
+
 int orc_kron_sample(uint32_t n0, const float *W, uint32_t k, uint64_t e_begin, uint64_t e_end,
                     uint64_t seed, uint32_t gid, int64_t *src, int64_t *dst)
 {
@@ -136,8 +145,8 @@ int orc_kron_sample(uint32_t n0, const float *W, uint32_t k, uint64_t e_begin, u
         uint64_t u = 0, v = 0;
         uint32_t blk[4] = {0, 0, 0, 0};
         for (uint32_t l = 0; l < k; ++l) {
-            if (l % 4 == 0) draw(seed, e, l / 4, TAG_KRON, gid, blk);
-            uint32_t c = cell_of(blk[l % 4], thr, C);
+            if (l % 5 == 0) draw(seed, e, l / 5, TAG_KRON, gid, blk);
+            uint32_t c = cell_of(level_uniform24(blk, l % 5) << 8, thr, C);
             u = u * n0 + c / n0;
             v = v * n0 + c % n0;
         }

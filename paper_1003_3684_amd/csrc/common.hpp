@@ -103,6 +103,15 @@ __device__ __forceinline__ Block4 philox(uint32_t c0, uint32_t c1, uint32_t c2, 
     return Block4{c0, c1, c2, c3};
 }
 
+// The Kronecker sampler takes five 24-bit uniforms from a Philox block: the
+// top 24 bits of words 0..3, and the low bytes of words 0, 1 and 2.  Each is
+// used as a 32-bit word with its low 8 bits zero, so levels 0..3 read their
+// word as it is (compared with thresholds that are multiples of 256, the low
+// byte cannot change the cell) and level 4 reads this one.
+__device__ __forceinline__ uint32_t level4_word(const Block4 &r) {
+    return ((r.w0 & 255u) << 24) | ((r.w1 & 255u) << 16) | ((r.w2 & 255u) << 8);
+}
+
 // floor(U * R / 2^64): an index in [0, R) from a 64-bit uniform.
 __device__ __forceinline__ uint64_t uidx64(uint64_t U, uint64_t R) { return __umul64hi(U, R); }
 

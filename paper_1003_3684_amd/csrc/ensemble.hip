@@ -91,12 +91,12 @@ __global__ __launch_bounds__(kKronThreads) void kron_batch(const KGraph *G, uint
         const uint32_t pow2 = uniform32(s_g.pow2), tagword = uniform32(s_g.tagword);
         const uint32_t key0 = uniform32(s_g.key0), key1 = uniform32(s_g.key1);
         __syncthreads();  // s_g is rewritten by the next tile
-        // Levels 4 blk .. 4 blk + nlev - 1 of edge e from Philox block blk.
+        // Levels 5 blk .. 5 blk + nlev - 1 of edge e from Philox block blk.
         auto levels = [&](uint64_t e, uint32_t blk, uint32_t nlev, uint32_t &u, uint32_t &v) {
             const Block4 r = philox((uint32_t)e, (uint32_t)(e >> 32), blk, tagword, key0, key1);
-            const uint32_t ws[4] = {r.w0, r.w1, r.w2, r.w3};
+            const uint32_t ws[5] = {r.w0, r.w1, r.w2, r.w3, level4_word(r)};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
+            for (int i = 0; i < 5; ++i) {
                 if ((uint32_t)i < nlev) {
                     const uint32_t b = bucket_of<NT>(ws[i], tm1);
                     const uint32_t rd = (uint32_t)(lut_row >> (4 * b)) & 15u;
@@ -111,13 +111,13 @@ __global__ __launch_bounds__(kKronThreads) void kron_batch(const KGraph *G, uint
                 }
             }
         };
-        const uint32_t full = k / 4, rest = k % 4;
+        const uint32_t full = k / 5, rest = k % 5;
         const uint64_t e0 = (tile - block0) * (uint64_t)(kKronThreads * ITEMS);
         for (int it = 0; it < ITEMS; ++it) {
             const uint64_t e = e0 + (uint64_t)it * kKronThreads + threadIdx.x;
             if (e >= edges) break;
             uint32_t u = 0, v = 0;  // below n0^k <= 2^32
-            for (uint32_t blk = 0; blk < full; ++blk) levels(e, blk, 4, u, v);
+            for (uint32_t blk = 0; blk < full; ++blk) levels(e, blk, 5, u, v);
             if (rest) levels(e, full, rest, u, v);
             src[ebase + e] = (IdT)(vbase + u);
             dst[ebase + e] = (IdT)(vbase + v);

@@ -44,12 +44,17 @@ int build_sample_table(uint32_t n0, const float *W, SampleTable &tab) {
         run[c] = S;
     }
     if (!(S > 0.0) || std::isinf(S)) return fail(SFG_EINVAL, "kron_generate: initiator sums to zero or overflows");
-    // thr[c] = floor(S_c / T * 2^32) for c < C-1; thr[C-1] = 2^32 (never reached).
+    // thr[c] = floor(S_c / T * 2^32) for c < C-1; thr[C-1] = 2^32 (never
+    // reached).  A level's 24-bit uniform U selects #{c : 256 U >= thr[c]};
+    // the kernels compare the whole 32-bit word w (U in its top 24 bits) with
+    // thr rounded up to a multiple of 256, which selects the same cell
+    // whatever w's low byte holds.
     std::vector<uint64_t> thr(C);
     for (uint32_t c = 0; c + 1 < C; ++c) {
         const double q = run[c] / S;
         const double t = std::floor(q * 4294967296.0);
-        thr[c] = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
+        const uint64_t t32 = t >= 4294967296.0 ? (1ull << 32) : (uint64_t)t;
+        thr[c] = std::min<uint64_t>(1ull << 32, (t32 + 255) & ~255ull);
     }
     thr[C - 1] = 1ull << 32;
     // cell(w) = #{c < C-1 : w >= thr[c]}; thresholds equal to 0 always count.
@@ -153,22 +158,22 @@ __global__ __launch_bounds__(kFastBlock) void kron_sample_fast(FastArgs a, IdT *
         }
     }
     if (kGuide || CNT) __syncthreads();
-    // Levels 4 blk .. 4 blk + nlev - 1 of edge (elo, ehi) from Philox block blk.
+    // Levels 5 blk .. 5 blk + nlev - 1 of edge (elo, ehi) from Philox block blk.
     auto levels = [&](uint32_t elo, uint32_t ehi, uint32_t blk, uint32_t nlev, AccT &u, AccT &v) {
         const Block4 r = philox(elo, ehi, blk, a.tagword, a.key0, a.key1);
-        const uint32_t ws[4] = {r.w0, r.w1, r.w2, r.w3};
+        const uint32_t ws[5] = {r.w0, r.w1, r.w2, r.w3, level4_word(r)};
         // The block's table reads go out together; the rare words whose
         // prefix holds a threshold are decoded by comparison.
-        uint32_t rd[4], cd[4];
+        uint32_t rd[5], cd[5];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 5; ++i) {
             const uint32_t g = ws[i] >> (32 - kGuideBits);
             rd[i] = kGuide ? (uint32_t)s_guide[g] : kStraddle;
             cd[i] = kGuide ? (uint32_t)s_guide[kGuideSize + g] : 0u;
         }
-        if ((rd[0] | rd[1] | rd[2] | rd[3]) & kStraddle) {
+        if ((rd[0] | rd[1] | rd[2] | rd[3] | rd[4]) & kStraddle) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 5; ++i)
                 if (rd[i] & kStraddle) {
                     const uint32_t b = bucket_of<NT>(ws[i], a.tm1);
                     rd[i] = (uint32_t)(a.lut_row >> (4 * b)) & 15u;
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(kFastBlock) void kron_sample_fast(FastArgs a, IdT *
                 }
         }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 5; ++i) {
             if ((uint32_t)i < nlev) {
                 if (POW2) {
                     u = (u << a.shift) | (AccT)rd[i];
@@ -188,14 +193,14 @@ __global__ __launch_bounds__(kFastBlock) void kron_sample_fast(FastArgs a, IdT *
             }
         }
     };
-    // Whole blocks of four levels first (no per-level test), then the rest.
-    const uint32_t full = a.k / 4, rest = a.k % 4;
+    // Whole blocks of five levels first (no per-level test), then the rest.
+    const uint32_t full = a.k / 5, rest = a.k % 5;
     const uint64_t stride = (uint64_t)gridDim.x * kFastBlock;
     for (uint64_t i = (uint64_t)blockIdx.x * kFastBlock + threadIdx.x; i < a.num_edges; i += stride) {
         AccT u = 0, v = 0;
         const uint64_t e = a.e_begin + i;  // the edge's index in the whole graph
         const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
-        for (uint32_t blk = 0; blk < full; ++blk) levels(elo, ehi, blk, 4, u, v);
+        for (uint32_t blk = 0; blk < full; ++blk) levels(elo, ehi, blk, 5, u, v);
         if (rest) levels(elo, ehi, full, rest, u, v);
         src[i] = (IdT)u;
         dst[i] = (IdT)v;
@@ -261,12 +266,12 @@ __global__ __launch_bounds__(kBlock) void kron_sample_general(GeneralArgs a, Sam
         AccT u = 0, v = 0;
         const uint64_t e = a.e_begin + i;  // the edge's index in the whole graph
         const uint32_t elo = (uint32_t)e, ehi = (uint32_t)(e >> 32);
-        for (uint32_t blk = 0; blk * 4 < a.k; ++blk) {
+        for (uint32_t blk = 0; blk * 5 < a.k; ++blk) {
             const Block4 r = philox(elo, ehi, blk, a.tagword, a.key0, a.key1);
-            const uint32_t ws[4] = {r.w0, r.w1, r.w2, r.w3};
+            const uint32_t ws[5] = {r.w0, r.w1, r.w2, r.w3, level4_word(r)};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if (blk * 4 + i < a.k) {
+            for (int i = 0; i < 5; ++i) {
+                if (blk * 5 + i < a.k) {
                     // b = #{j : w > s_t[j]}: binary search over the padded sorted table.
                     const uint32_t w = ws[i];
                     uint32_t b = 0;

@@ -116,13 +116,17 @@ def _cell_probs(orc, W):
 @pytest.mark.parametrize("n0,k,W", [
     (2, 3, [[0.6, 0.25], [0.1, 0.05]]),
     (3, 2, [[0.3, 0.1, 0.05], [0.2, 0.02, 0.1], [0.0, 0.15, 0.08]]),
+    (2, 6, [[0.35, 0.25], [0.22, 0.18]]),
 ])
 @pytest.mark.parametrize("seed", [11, 12])
 def test_kron_chi_square_tiny(orc, n0, k, W, seed):
     """Every (u, v) cell of the n0^k x n0^k matrix is hit with probability
     prod_l p(u_l, v_l), the Kronecker product of the quantized initiator
     (brute-force enumeration of all cells, chi-square over 10^6 edges).  The
-    initiators are asymmetric, so a transposed digit would fail."""
+    initiators are asymmetric, so a transposed digit would fail; k = 6 spans
+    a whole Philox block of five levels (the fifth built from the low bytes
+    of three words) and the first level of the next, so levels that shared
+    random bits would fail too."""
     E = 1_000_000
     src, dst = orc.kron_sample(n0, W, k, E, seed)
     nv = n0 ** k
