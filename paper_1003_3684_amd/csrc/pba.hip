@@ -644,6 +644,217 @@ template <typename IdT> __global__ __launch_bounds__(kSubThreads) void pba_subst
     }
 }
 
+// Whole-tile substitution of one graph with at most 1,024 labels (tiles of
+// at most 16,384 slots).  One workgroup per CU walks a contiguous range of
+// tiles of its XCD (so the 32 workgroups of an XCD hold neighbouring tiles,
+// which read neighbouring pieces of every list), sorts each whole tile by
+// label in LDS with the same stable ranks as above, and gathers every
+// label's run of list entries for the tile at once: a run is one request
+// instead of one per sub-tile.  The next tile's labels and list positions
+// are loaded while the current tile is ranked, and tile coordinates come
+// from the partition bounds, so no load waits on another inside a tile.
+// LDS (138 KB) is reused: the per-wave counts and the ranks share the space
+// that the gathered values take once the permutation is built.
+constexpr int kTileThreads = 1024;
+constexpr int kTileWaves = kTileThreads / 64;
+constexpr uint32_t kTileMax = 16384;
+constexpr int kTilePer = (int)kTileMax / kTileThreads;  // slots of a thread
+constexpr uint32_t kTilePmax = 1024;
+static_assert(kTilePer == 16 && kTilePmax <= (uint32_t)kTileThreads, "one label per thread in the label scans");
+
+template <typename IdT> __global__ __launch_bounds__(kTileThreads) void pba_substitute_tile(SubArgs a) {
+    __shared__ uint64_t s_cur[kTilePmax];                 // list entry of each label's first slot in the tile
+    __shared__ uint16_t s_lab[kTileMax];                  // labels, slot order
+    __shared__ uint16_t s_off[kTilePmax];                 // label bases in sorted order
+    __shared__ uint16_t s_perm[kTileMax];                 // slot of each sorted position
+    __shared__ uint32_t s_part[kTileWaves];
+    __shared__ uint32_t s_u[kTileMax];  // per-wave label counts [kTileWaves][Pm] and ranks [kTileMax], then values
+    uint16_t *s_wcnt = reinterpret_cast<uint16_t *>(s_u);
+    uint16_t *s_rank = s_wcnt + kTileWaves * kTilePmax;
+    uint32_t *s_val = s_u;
+    static_assert(kTileWaves * kTilePmax * 2 + kTileMax * 2 <= kTileMax * 4, "counts and ranks share the values' space");
+    const PGraph &p = a.G.one;  // a single graph
+    const uint32_t P = p.P;
+    const uint32_t xcd = blockIdx.x % kXcd, nper = gridDim.x / kXcd;
+    const uint64_t lt_end = std::min<uint64_t>(a.tiles, (uint64_t)(xcd + 1) * a.per_xcd);
+    uint64_t lt = (uint64_t)xcd * a.per_xcd + blockIdx.x / kXcd;
+    uint32_t lbits = 0;
+    while ((1u << lbits) < P) ++lbits;
+    const uint64_t pq = p.n / P;
+    const uint32_t pr = (uint32_t)(p.n % P), pmagic = 0xFFFFFFFFu / P, mmagic = 0xFFFFFFFFu / p.m;
+    IdT *src = static_cast<IdT *>(a.src), *dst = static_cast<IdT *>(a.dst);
+
+    // Tile lt covers slots [first, first + nsub) of partition q, whose slots
+    // start at b0; false for a tile past the partition's end.
+    uint32_t q = 0, nsub = 0;
+    uint64_t b0 = 0, first = 0;
+    auto tile_of = [&](uint64_t t, uint32_t &tq, uint32_t &tn, uint64_t &tb0, uint64_t &tfirst) -> bool {
+        tq = (uint32_t)(t / a.T1max);
+        const uint32_t tau = (uint32_t)(t % a.T1max);
+        if (tau >= p.T1) return false;
+        // The partition's slots, from its vertex range (no loads).
+        const uint64_t v0 = part_start(tq, p.n, P), v1 = part_start(tq + 1, p.n, P);
+        tb0 = p.ebase + (uint64_t)p.m * v0;
+        const uint64_t len = (uint64_t)p.m * (v1 - v0);
+        tfirst = (uint64_t)tau * p.CT;
+        if (tfirst >= len) return false;
+        tn = (uint32_t)std::min<uint64_t>(p.CT, len - tfirst);
+        return true;
+    };
+    // A tile's labels (thread: 16 slots, wave w holding slots w*1024 ..
+    // w*1024+1023) and the two parts of label tid's list position.
+    uint32_t lr[kTilePer];
+    uint64_t cur_a = 0;
+    uint32_t cur_b = 0;
+    auto load_tile = [&](uint32_t tq, uint32_t tn, uint64_t tb0, uint64_t tfirst) {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int st = 0; st < kTilePer; ++st) {
+            const uint32_t i = (uint32_t)(tid >> 6) * 1024u + (uint32_t)st * 64u + (tid & 63);
+            lr[st] = a.lab[tb0 + tfirst + (i < tn ? i : tn - 1)];
+        }
+        const uint32_t tau = (uint32_t)(tfirst / p.CT);
+        if ((uint32_t)tid < P) {
+            cur_a = a.sbase[p.seg0 + tid];
+            cur_b = a.H[p.H0 + ((uint64_t)tq * p.T1 + tau) * P + tid];
+        }
+    };
+
+    bool have = false;
+    while (lt < lt_end && !(have = tile_of(lt, q, nsub, b0, first))) lt += nper;
+    if (!have) return;
+    load_tile(q, nsub, b0, first);
+    while (have) {
+        // Lane indices made opaque per tile, so that the compiler does not
+        // keep every slot address of the loop live across it.
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const uint32_t lane = (uint32_t)tid & 63u, w = (uint32_t)tid >> 6;
+        // This tile's labels and list positions into LDS, counts cleared.
+#pragma unroll
+        for (int st = 0; st < kTilePer; ++st) {
+            const uint32_t i = w * 1024u + (uint32_t)st * 64u + lane;
+            if (i < nsub) s_lab[i] = (uint16_t)lr[st];
+        }
+        if ((uint32_t)tid < P) s_cur[tid] = cur_a + cur_b;
+        uint16_t *wcnt = s_wcnt + w * kTilePmax;
+        for (uint32_t l = lane; l < P; l += 64) wcnt[l] = 0;
+        // The next tile's labels are loaded while this one is processed.
+        uint32_t nq = 0, nn = 0;
+        uint64_t nb0 = 0, nfirst = 0;
+        bool next = false;
+        lt += nper;
+        while (lt < lt_end && !(next = tile_of(lt, nq, nn, nb0, nfirst))) lt += nper;
+        if (next) load_tile(nq, nn, nb0, nfirst);
+        __builtin_amdgcn_wave_barrier();
+        // Stable ranks inside each wave's 1,024 slots: every ballot over one
+        // label bit keeps the lanes that agree with this lane on that bit.
+        // Four steps at a time, so that their ballot chains interleave.
+        for (int st = 0; st < kTilePer; st += 4) {
+            uint32_t ii[4], ll[4];
+            bool vv[4];
+            uint64_t pp[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                ii[u] = w * 1024u + (uint32_t)(st + u) * 64u + lane;
+                vv[u] = ii[u] < nsub;
+                ll[u] = vv[u] ? s_lab[ii[u]] : 0u;
+                pp[u] = __ballot(vv[u]);
+            }
+            for (uint32_t bb = 0; bb < lbits; ++bb) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool bt = (ll[u] >> bb) & 1u;
+                    const uint64_t m = __ballot(bt);
+                    pp[u] &= bt ? m : ~m;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t pu = vv[u] ? pp[u] : 0ull;
+                const uint32_t below = count_below(pu);
+                const uint32_t kk = wcnt[ll[u]];
+                s_rank[ii[u]] = (uint16_t)(kk + below);
+                __builtin_amdgcn_wave_barrier();
+                if (vv[u] && below == 0) wcnt[ll[u]] = (uint16_t)(kk + (uint32_t)__popcll(pu));
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        __syncthreads();
+        // Label tid: prefix over the waves, then the label bases by a block scan.
+        uint32_t cnt = 0;
+        if ((uint32_t)tid < P) {
+#pragma unroll
+            for (int wv = 0; wv < kTileWaves; ++wv) {
+                const uint32_t c = s_wcnt[wv * kTilePmax + tid];
+                s_wcnt[wv * kTilePmax + tid] = (uint16_t)cnt;
+                cnt += c;
+            }
+        }
+        uint32_t xs = cnt;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(xs, off, 64);
+            if (lane >= (uint32_t)off) xs += y;
+        }
+        if (lane == 63) s_part[w] = xs;
+        __syncthreads();
+        uint32_t run = xs - cnt;
+        for (uint32_t wv = 0; wv < w; ++wv) run += s_part[wv];
+        if ((uint32_t)tid < P) s_off[tid] = (uint16_t)run;
+        __syncthreads();
+        // Sorted position of every slot.
+#pragma unroll 4
+        for (int st = 0; st < kTilePer; ++st) {
+            const uint32_t i = w * 1024u + (uint32_t)st * 64u + lane;
+            if (i < nsub) {
+                const uint32_t l = s_lab[i];
+                s_perm[s_off[l] + s_wcnt[w * kTilePmax + l] + s_rank[i]] = (uint16_t)i;
+            }
+        }
+        __syncthreads();  // the counts are dead: their space takes the values
+        // Gather in sorted order.
+        uint32_t v[kTilePer];
+#pragma unroll
+        for (int k = 0; k < kTilePer; ++k) {
+            const uint32_t i = (uint32_t)k * kTileThreads + tid;
+            const uint32_t ic = i < nsub ? i : nsub - 1;  // a valid address for every lane
+            const uint32_t l = s_lab[s_perm[ic]];
+            v[k] = a.sel[s_cur[l] + (ic - s_off[l])];
+        }
+        // Unconditional stores: a lane past the tile's end repeats the last
+        // slot's store with the same value (a conditional store would let
+        // the compiler sink its load behind the wait for all of them).
+#pragma unroll
+        for (int k = 0; k < kTilePer; ++k) {
+            const uint32_t i = (uint32_t)k * kTileThreads + tid;
+            s_val[s_perm[i < nsub ? i : nsub - 1]] = v[k];
+        }
+        __syncthreads();
+        // Edges in slot order.
+        const uint64_t vstart = p.vbase + part_start(q, p.n, P);
+#pragma unroll 4
+        for (int k = 0; k < kTilePer; ++k) {
+            const uint32_t i = (uint32_t)k * kTileThreads + tid;
+            if (i < nsub) {
+                const uint64_t j = first + i;
+                const uint32_t l = s_lab[i];
+                const uint64_t e = b0 + j;
+                const uint64_t jm = div_magic32((uint32_t)j, p.m, mmagic);
+                const uint64_t lstart = (uint64_t)l * pq + div_magic32(l * pr, P, pmagic);
+                src[e] = (IdT)(vstart + jm);
+                dst[e] = (IdT)(p.vbase + lstart + s_val[i]);
+            }
+        }
+        __syncthreads();  // s_lab, s_val and s_cur are rewritten by the next tile
+        have = next;
+        q = nq;
+        nsub = nn;
+        b0 = nb0;
+        first = nfirst;
+    }
+}
+
 uint32_t choose_ct(uint64_t P) {
     // Tiles of the count/substitution passes: large enough that the P x P
     // histogram rows stay a small fraction of the slot arrays.
@@ -788,7 +999,6 @@ static int enqueue(const PbaPlan &pl, const Graphs &G, const Factions &fac, uint
     uint64_t *xpre = reinterpret_cast<uint64_t *>(ws + pl.off_xpre);
     uint64_t *xtot = reinterpret_cast<uint64_t *>(ws + pl.off_xtot);
     uint32_t *queues = reinterpret_cast<uint32_t *>(ws + pl.off_queues);
-    (void)count;
     const int cus = device_cu_count();
     const int res_grid = cus * 8;
     const uint32_t S = pl.S;
@@ -841,7 +1051,13 @@ static int enqueue(const PbaPlan &pl, const Graphs &G, const Factions &fac, uint
     const unsigned gsub = (unsigned)(per_xcd * kXcd);
     {
         ProfScope _ps("pba_substitute", s);
-        if (id_bytes == 4)
+        if (count == 1 && pl.Pmax <= kTilePmax) {
+            const unsigned gt = (unsigned)std::min<uint64_t>((uint64_t)cus, (per_xcd) * kXcd) / kXcd * kXcd;
+            if (id_bytes == 4)
+                pba_substitute_tile<int32_t><<<std::max(gt, (unsigned)kXcd), kTileThreads, 0, s>>>(sa);
+            else
+                pba_substitute_tile<int64_t><<<std::max(gt, (unsigned)kXcd), kTileThreads, 0, s>>>(sa);
+        } else if (id_bytes == 4)
             pba_substitute<int32_t><<<gsub, kSubThreads, lds, s>>>(sa);
         else
             pba_substitute<int64_t><<<gsub, kSubThreads, lds, s>>>(sa);
