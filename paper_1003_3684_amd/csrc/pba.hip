@@ -351,9 +351,18 @@ __global__ __launch_bounds__(256) void pba_count(CountArgs a) {
             const uint64_t j = j0 + (uint64_t)u * 256;
             l[u] = j < last ? a.lab[b0 + j] : 0u;
         }
+        // The partition's own label is the most frequent one (every chain
+        // that reaches the first slot ends there): its lanes are counted by
+        // a ballot instead of contending for one LDS word.
+        uint32_t own = 0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (j0 + (uint64_t)u * 256 < last) atomicAdd(&s_h[l[u]], 1u);
+        for (int u = 0; u < 8; ++u) {
+            const bool in = j0 + (uint64_t)u * 256 < last;
+            const bool mine = in && l[u] == q;
+            own += (uint32_t)__popcll(__ballot(mine));
+            if (in && !mine) atomicAdd(&s_h[l[u]], 1u);
+        }
+        if ((threadIdx.x & 63) == 0 && own) atomicAdd(&s_h[q], own);
     }
     __syncthreads();
     uint32_t *row = a.H + p.H0 + ((uint64_t)q * p.T1 + tau) * p.P;
