@@ -673,9 +673,10 @@ static_assert(kTilePer == 16 && kTilePmax <= (uint32_t)kTileThreads, "one label 
 
 template <typename IdT> __global__ __launch_bounds__(kTileThreads) void pba_substitute_tile(SubArgs a) {
     __shared__ uint64_t s_cur[kTilePmax];                 // list entry of each label's first slot in the tile
-    __shared__ uint16_t s_lab[kTileMax];                  // labels, slot order
     __shared__ uint16_t s_off[kTilePmax];                 // label bases in sorted order
-    __shared__ uint16_t s_perm[kTileMax];                 // slot of each sorted position
+    __shared__ uint32_t s_r1[kTileMax];  // labels in slot order (u16), then slot | label << 14 of each sorted position
+    uint16_t *s_lab = reinterpret_cast<uint16_t *>(s_r1);
+    uint32_t *s_perm = s_r1;
     __shared__ uint32_t s_part[kTileWaves];
     __shared__ uint32_t s_u[kTileMax];  // per-wave label counts [kTileWaves][Pm] and ranks [kTileMax], then values
     uint16_t *s_wcnt = reinterpret_cast<uint16_t *>(s_u);
@@ -812,13 +813,21 @@ template <typename IdT> __global__ __launch_bounds__(kTileThreads) void pba_subs
         for (uint32_t wv = 0; wv < w; ++wv) run += s_part[wv];
         if ((uint32_t)tid < P) s_off[tid] = (uint16_t)run;
         __syncthreads();
-        // Sorted position of every slot.
+        // Sorted position of every slot (its label and rank first taken
+        // into registers: the permutation overwrites the labels).
+        uint32_t lk[kTilePer];
+#pragma unroll
+        for (int st = 0; st < kTilePer; ++st) {
+            const uint32_t i = w * 1024u + (uint32_t)st * 64u + lane;
+            lk[st] = i < nsub ? (uint32_t)s_lab[i] | ((uint32_t)s_rank[i] << 16) : 0u;
+        }
+        __syncthreads();
 #pragma unroll 4
         for (int st = 0; st < kTilePer; ++st) {
             const uint32_t i = w * 1024u + (uint32_t)st * 64u + lane;
             if (i < nsub) {
-                const uint32_t l = s_lab[i];
-                s_perm[s_off[l] + s_wcnt[w * kTilePmax + l] + s_rank[i]] = (uint16_t)i;
+                const uint32_t l = lk[st] & 0xFFFFu;
+                s_perm[s_off[l] + s_wcnt[w * kTilePmax + l] + (lk[st] >> 16)] = i | (l << 14);
             }
         }
         __syncthreads();  // the counts are dead: their space takes the values
@@ -828,16 +837,21 @@ template <typename IdT> __global__ __launch_bounds__(kTileThreads) void pba_subs
         for (int k = 0; k < kTilePer; ++k) {
             const uint32_t i = (uint32_t)k * kTileThreads + tid;
             const uint32_t ic = i < nsub ? i : nsub - 1;  // a valid address for every lane
-            const uint32_t l = s_lab[s_perm[ic]];
+            const uint32_t l = s_perm[ic] >> 14;
             v[k] = a.sel[s_cur[l] + (ic - s_off[l])];
         }
         // Unconditional stores: a lane past the tile's end repeats the last
         // slot's store with the same value (a conditional store would let
         // the compiler sink its load behind the wait for all of them).
+        // The values stored are the local destinations: the label's first
+        // vertex plus the endpoint (below 2^32: checked on the host).
 #pragma unroll
         for (int k = 0; k < kTilePer; ++k) {
             const uint32_t i = (uint32_t)k * kTileThreads + tid;
-            s_val[s_perm[i < nsub ? i : nsub - 1]] = v[k];
+            const uint32_t x = s_perm[i < nsub ? i : nsub - 1];
+            const uint32_t l = x >> 14;
+            const uint32_t lstart = l * (uint32_t)pq + div_magic32(l * pr, P, pmagic);
+            s_val[x & (kTileMax - 1)] = lstart + v[k];
         }
         __syncthreads();
         // Edges in slot order.
@@ -847,15 +861,13 @@ template <typename IdT> __global__ __launch_bounds__(kTileThreads) void pba_subs
             const uint32_t i = (uint32_t)k * kTileThreads + tid;
             if (i < nsub) {
                 const uint64_t j = first + i;
-                const uint32_t l = s_lab[i];
                 const uint64_t e = b0 + j;
                 const uint64_t jm = div_magic32((uint32_t)j, p.m, mmagic);
-                const uint64_t lstart = (uint64_t)l * pq + div_magic32(l * pr, P, pmagic);
                 src[e] = (IdT)(vstart + jm);
-                dst[e] = (IdT)(p.vbase + lstart + s_val[i]);
+                dst[e] = (IdT)(p.vbase + s_val[i]);
             }
         }
-        __syncthreads();  // s_lab, s_val and s_cur are rewritten by the next tile
+        __syncthreads();  // the labels, the values and s_cur are rewritten by the next tile
         have = next;
         q = nq;
         nsub = nn;
@@ -1060,7 +1072,7 @@ static int enqueue(const PbaPlan &pl, const Graphs &G, const Factions &fac, uint
     const unsigned gsub = (unsigned)(per_xcd * kXcd);
     {
         ProfScope _ps("pba_substitute", s);
-        if (count == 1 && pl.Pmax <= kTilePmax) {
+        if (count == 1 && pl.Pmax <= kTilePmax && G.one.n < (1ull << 32)) {
             const unsigned gt = (unsigned)std::min<uint64_t>((uint64_t)cus, (per_xcd) * kXcd) / kXcd * kXcd;
             if (id_bytes == 4)
                 pba_substitute_tile<int32_t><<<std::max(gt, (unsigned)kXcd), kTileThreads, 0, s>>>(sa);
