@@ -73,6 +73,13 @@ def test_pba_many_partitions(sfg, orc):
     _compare(sfg, orc, dict(n=2 * 1024, m=3, num_parts=1024, p_inter=0.05, seed=10))
 
 
+def test_pba_whole_tile_ragged(sfg, orc):
+    """Between 513 and 1,024 partitions the count tiles hold 16,384 slots: partitions spanning several
+    tiles with a ragged last one, for both id widths (the whole-tile substitution of one graph)."""
+    _compare(sfg, orc, dict(n=1000 * 7000 + 123, m=5, num_parts=1000, p_inter=0.1, seed=21))
+    _compare(sfg, orc, dict(n=600 * 3001 + 7, m=7, num_parts=600, p_inter=0.3, seed=22, id_bytes=8))
+
+
 @pytest.mark.parametrize("cfg", wl.PBA_SCALE, ids=[c["name"] for c in wl.PBA_SCALE])
 @pytest.mark.timeout(900)
 def test_pba_scale_full(sfg, orc, cfg):
