@@ -369,6 +369,31 @@ __global__ __launch_bounds__(256) void pba_count(CountArgs a) {
     for (uint32_t l = threadIdx.x; l < p.P; l += 256) row[l] = s_h[l];
 }
 
+// In-place exclusive prefix sum of n words spaced stride apart, starting from
+// acc; returns the total.  Sixteen loads go out together before their
+// stores: in a load-store-load chain every load would also wait for the
+// store before it.
+__device__ __forceinline__ uint64_t scan_strided(uint32_t *x, uint64_t n, uint64_t stride, uint64_t acc) {
+    constexpr int kBatch = 16;
+    uint64_t r = 0;
+    for (; r + kBatch <= n; r += kBatch) {
+        uint32_t v[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) v[u] = x[(r + u) * stride];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            x[(r + u) * stride] = (uint32_t)acc;
+            acc += v[u];
+        }
+    }
+    for (; r < n; ++r) {
+        const uint32_t v = x[r * stride];
+        x[r * stride] = (uint32_t)acc;
+        acc += v;
+    }
+    return acc;
+}
+
 // Column-wise exclusive scan of every graph's H block.  Column c of the batch
 // is label c - seg0 of the graph owning segment c; D[c] receives its total.
 __global__ __launch_bounds__(256) void pba_scan_columns(Graphs G, uint32_t S, uint32_t *H, uint64_t *D,
@@ -379,13 +404,7 @@ __global__ __launch_bounds__(256) void pba_scan_columns(Graphs G, uint32_t S, ui
     const PGraph &p = G.of_seg(c, g);
     const uint32_t l = c - p.seg0;
     const uint64_t rows = (uint64_t)p.P * p.T1;
-    uint32_t *col = H + p.H0 + l;
-    uint64_t acc = 0;
-    for (uint64_t r = 0; r < rows; ++r) {
-        const uint32_t v = col[r * p.P];
-        col[r * p.P] = (uint32_t)acc;
-        acc += v;
-    }
+    const uint64_t acc = scan_strided(H + p.H0 + l, rows, p.P, 0);
     D[c] = acc;
     if (acc >= kTerm) raise_device_error(err, DEVERR_QUEUE);  // a list longer than 2^31 is unsupported
 }
@@ -405,12 +424,7 @@ __global__ __launch_bounds__(256) void pba_scan_groups(uint32_t *part, uint64_t 
                                                        uint32_t *err) {
     const uint32_t col = blockIdx.x * 256 + threadIdx.x;
     if (col >= P) return;
-    uint64_t acc = 0;
-    for (uint64_t g = 0; g < groups; ++g) {
-        const uint32_t c = part[g * P + col];
-        part[g * P + col] = (uint32_t)acc;
-        acc += c;
-    }
+    const uint64_t acc = scan_strided(part + col, groups, P, 0);
     D[col] = acc;
     if (acc >= kTerm) raise_device_error(err, DEVERR_QUEUE);
 }
@@ -420,12 +434,7 @@ __global__ __launch_bounds__(256) void pba_scan_apply(uint32_t *H, uint64_t R, u
     if (col >= P) return;
     const uint64_t r0 = (uint64_t)blockIdx.x * kScanRows;
     const uint64_t r1 = std::min<uint64_t>(R, r0 + kScanRows);
-    uint32_t acc = part[(uint64_t)blockIdx.x * P + col];
-    for (uint64_t r = r0; r < r1; ++r) {
-        const uint32_t c = H[r * P + col];
-        H[r * P + col] = acc;
-        acc += c;
-    }
+    scan_strided(H + r0 * P + col, r1 - r0, P, part[(uint64_t)blockIdx.x * P + col]);
 }
 
 // List bases: sbase = exclusive prefix of D over all segments (single block).
