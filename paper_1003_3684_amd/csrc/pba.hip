@@ -671,14 +671,17 @@ template <typename IdT> __global__ __launch_bounds__(kSubThreads) void pba_subst
 // instead of one per sub-tile.  The next tile's labels and list positions
 // are loaded while the current tile is ranked, and tile coordinates come
 // from the partition bounds, so no load waits on another inside a tile.
-// LDS (138 KB) is reused: the per-wave counts and the ranks share the space
-// that the gathered values take once the permutation is built.
+// LDS (138 KB) is reused: the permutation words (slot | label << 14) take
+// the labels' space once every slot's label and rank are in registers, and
+// the gathered values (local destinations) take the space of the per-wave
+// counts and the ranks.
 constexpr int kTileThreads = 1024;
 constexpr int kTileWaves = kTileThreads / 64;
 constexpr uint32_t kTileMax = 16384;
 constexpr int kTilePer = (int)kTileMax / kTileThreads;  // slots of a thread
 constexpr uint32_t kTilePmax = 1024;
 static_assert(kTilePer == 16 && kTilePmax <= (uint32_t)kTileThreads, "one label per thread in the label scans");
+static_assert(kTileMax <= (1u << 14), "a slot fits the permutation word's low 14 bits");
 
 template <typename IdT> __global__ __launch_bounds__(kTileThreads) void pba_substitute_tile(SubArgs a) {
     __shared__ uint64_t s_cur[kTilePmax];                 // list entry of each label's first slot in the tile
