@@ -83,6 +83,49 @@ def _valu_per_edge_from_profile():
         return None
 
 
+# Algorithmic HBM bytes per PBA edge, from the method's data flow: a slot's
+# label written and read twice at 2 B (6), a 4-byte rank per slot for the
+# exchange written and read (8; here the ranks stay in LDS), the selection
+# lists written and gathered (8), the edge written (8) -- about 30 B.
+PBA_BYTES_PER_EDGE = 30
+
+
+def _pba_profile_values():
+    """HBM bytes per PBA generation at 2^27 and 2^30 vertices from the
+    committed rocprofv3 counter summary, or {} if it was taken on a different
+    source of the PBA kernels."""
+    h = hashlib.sha256()
+    for f in ("pba.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_1003_3684_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    path = os.path.join(ROOT, "profiles", "pba_kernels_n2e27_n2e30.txt")
+    if not os.path.exists(path):
+        return {}
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#") and not line.startswith("##"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("pba_source_sha256_16") != h.hexdigest()[:16]:
+        return {}
+    out = {}
+    for key in ("hbm_bytes_per_generation_n2e27", "hbm_bytes_per_generation_n2e30"):
+        try:
+            out[key] = float(vals[key])
+        except (KeyError, ValueError):
+            pass
+    return out
+
+
+def _pba_roofline(edges, ms, traffic):
+    """The PBA generation against HBM: PBA_BYTES_PER_EDGE per edge over the
+    generation's time (all its passes), beside the bytes the counters saw."""
+    achieved = edges * PBA_BYTES_PER_EDGE / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+            "traffic": traffic, "kernel": "pba_generate (all passes)", "algorithmic_bytes_per_edge": PBA_BYTES_PER_EDGE,
+            "note": "the chain walks are bound by L2 misses of one random read per element (see the PBA profile)"}
+
+
 def _host_info():
     """CPU model, usable cores and RAM of the host the CPU baseline ran on."""
     model, ram = "unknown", None
@@ -431,6 +474,7 @@ def _bench_pba_paper(sfg, wl, torch, reps=2):
     torch.cuda.empty_cache()
     return {"workload": c["name"], "edges": E, "gen_ms": ms, "gen_edges_per_s": E / (ms / 1e3),
             "kernels": kernels,
+            "roofline": _pba_roofline(E, ms, _pba_profile_values().get("hbm_bytes_per_generation_n2e30")),
             "paper_context": "under 13 s for 1e9 vertices and 5e9 edges on 1,024 processors of a cluster"}
 
 
@@ -467,7 +511,8 @@ def _bench_pba(sfg, wl, torch, reps=3, paths=True):
     gen_ms, csr_ms = a.elapsed_time(b) / reps, b.elapsed_time(d) / reps
     out = {"workload": c["name"], "edges": E, "gen_ms": gen_ms, "gen_edges_per_s": E / (gen_ms / 1e3),
            "csr_ms": csr_ms, "step_edges_per_s": E / ((gen_ms + csr_ms) / 1e3),
-           "kernels": _pba_breakdown(sfg, gen, reps)}
+           "kernels": _pba_breakdown(sfg, gen, reps),
+           "roofline": _pba_roofline(E, gen_ms, _pba_profile_values().get("hbm_bytes_per_generation_n2e27"))}
     if not paths:
         del src, dst, rp, col, ws
         torch.cuda.empty_cache()
