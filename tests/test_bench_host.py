@@ -61,6 +61,23 @@ def test_valu_reader_checks_the_sampler_hash(bench, tmp_path):
     assert bench._valu_per_edge_from_profile() is None
 
 
+def test_pba_traffic_reader_checks_the_pba_hash(bench, tmp_path):
+    csrc = tmp_path / "paper_1003_3684_amd" / "csrc"
+    _write(csrc / "pba.hip", "pba")
+    _write(csrc / "common.hpp", "shared")
+    h = hashlib.sha256(b"pbashared").hexdigest()[:16]
+    prof = tmp_path / "profiles" / "pba_kernels_n2e27_n2e30.txt"
+    assert bench._pba_profile_values() == {}
+    _write(prof, f"# note: x\n## PBA generation, 2^27 vertices: 7 generations\npba_source_sha256_16: {h}\n"
+                 "hbm_bytes_per_generation_n2e27: 2.5e+10\nhbm_bytes_per_generation_n2e30: n/a\n")
+    assert bench._pba_profile_values() == {"hbm_bytes_per_generation_n2e27": 2.5e10}  # malformed value dropped
+    _write(csrc / "pba.hip", "pba, edited")
+    assert bench._pba_profile_values() == {}
+    roof = bench._pba_roofline(1000, 1.0, None)
+    assert roof["achieved"] == 1000 * bench.PBA_BYTES_PER_EDGE / 1e-3 / 1e9 and roof["traffic"] is None
+    assert roof["frac"] == roof["achieved"] / roof["peak"]
+
+
 def test_host_info(bench):
     info = bench._host_info()
     assert set(info) == {"cpu", "usable_cores", "ram_gib"}
