@@ -875,8 +875,8 @@ template <typename IdT> __global__ __launch_bounds__(kTileThreads) void pba_subs
                 const uint64_t j = first + i;
                 const uint64_t e = b0 + j;
                 const uint64_t jm = div_magic32((uint32_t)j, p.m, mmagic);
-                src[e] = (IdT)(vstart + jm);
-                dst[e] = (IdT)(p.vbase + s_val[i]);
+                __builtin_nontemporal_store((IdT)(vstart + jm), &src[e]);
+                __builtin_nontemporal_store((IdT)(p.vbase + s_val[i]), &dst[e]);
             }
         }
         __syncthreads();  // the labels, the values and s_cur are rewritten by the next tile
